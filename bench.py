@@ -1,0 +1,321 @@
+#!/usr/bin/env python3
+"""Benchmark of the D2Q9 Shan-Chen step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A bench "step" is one pass of the whole hot path over the many-droplet
+workload: droplet initialisation, `--lbm-steps` (default 5000) fused
+stream-collide-force time steps, FP64 conservation + interface metrics, and
+the moments export, on a 4096 x 4096 periodic grid with 2000 droplets (centres
+uniform, R uniform in [8, 48], max-merged, tanh width 2, noise 1e-3), G = -5.5
+and tau = 1.0 (the paper's Sec. III-A values; tau = 0.8 diverges for this
+field).  Populations are FP32; the arithmetic is FP32.
+
+`value` is lattice updates per second (MLUPS) of the whole job with the inputs
+resident; `roofline` prices the step kernel (the dominant kernel) at 72
+algorithmic bytes per lattice update against the 8 TB/s HBM peak, with the
+kernel's average launch time measured by HIP events on its stream over the
+timed region.  Extra objects report the FP16-shifted storage, the batched
+parameter sweep, the serving loop and the FP64 oracle's CPU rate.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_F32 = 72   # 9 populations read + 9 written, 4 bytes each
+BYTES_F16 = 36
+
+
+def log(msg: str):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("sc_device.h", "sc_kernels.hip"):
+        with open(os.path.join(HERE, "paper_2504_10539_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(kernel_hash: str, key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None."""
+    path = os.path.join(HERE, "profiles", "step_counters.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = d.get(key)
+    if not e or e.get("kernel_hash") != kernel_hash:
+        return None
+    return e.get("bytes_per_launch")
+
+
+def run_main(args, torch, lbm, inputs):
+    N = args.n
+    drops = inputs.many_droplets(N, args.drops, 8, 48, seed=3)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted")):
+        if storage == lbm.LBM_F16_SHIFTED and args.no_fp16:
+            continue
+        rho0 = 0.5 if storage == lbm.LBM_F16_SHIFTED else 0.0
+        sim = lbm.Simulation(N, N, args.G, args.tau, storage, rho0)
+        sim.init_droplets(drops, seed=3)
+        if args.tile >= 0:
+            sim.set_tile(args.tile)
+        elif not args.no_autotune:
+            sim.autotune(reps=4)
+        rho = torch.empty((N, N), dtype=torch.float32, device="cuda")
+        ux = torch.empty_like(rho)
+        uy = torch.empty_like(rho)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+
+        def job(timed_step_events=None):
+            sim.init_droplets(drops, seed=3)
+            if timed_step_events:
+                timed_step_events[0].record(stream)
+            sim.step(args.lbm_steps)
+            if timed_step_events:
+                timed_step_events[1].record(stream)
+            m = sim.metrics()
+            lbm.LIB.lbm_moments(sim.handle, rho.data_ptr(), ux.data_ptr(), uy.data_ptr())
+            return m
+
+        for _ in range(args.warmup):
+            job()
+        torch.cuda.synchronize()
+        step_ms = []
+        t0 = time.perf_counter()
+        m = None
+        for _ in range(args.steps):
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+            m = job(evs)
+            step_ms.append(evs[0].elapsed_time(evs[1]))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lu = float(N) * N * args.lbm_steps * args.steps
+        launch_ms = sum(step_ms) / (args.lbm_steps * args.steps)
+        bpu = BYTES_F32 if storage == lbm.LBM_F32 else BYTES_F16
+        achieved = bpu * N * N / (launch_ms * 1e-3) / 1e9
+        out[name] = {
+            "mlups": lu / wall / 1e6,
+            "ms_per_job": wall * 1e3 / args.steps,
+            "step_kernel_ms": launch_ms,
+            "step_kernel_mlups": N * N / (launch_ms * 1e-3) / 1e6,
+            "achieved_gbs": achieved,
+            "bytes_per_update": bpu,
+            "tile": sim.tile,
+            "metrics": {k: m[k] for k in ("W", "Gmax", "drho", "W_eff", "E_int", "mass", "finite")},
+        }
+        log(f"[{name}] {out[name]['mlups']:.0f} MLUPS whole job, step kernel "
+            f"{launch_ms:.4f} ms = {achieved:.0f} GB/s ({achieved / HBM_PEAK_GBS:.3f} of peak)")
+        sim.close()
+        del rho, ux, uy
+        torch.cuda.empty_cache()
+    return out
+
+
+def run_copy_reference(torch, lbm):
+    n = 2 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        lbm.stream_copy(b, a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        lbm.stream_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n / (ms * 1e-3) / 1e9
+
+
+def run_sweep(args, torch, lbm, inputs):
+    """512 instances of 256^2 in one batched persistent launch per step."""
+    pairs = inputs.sweep_grid(32, 16)[: args.sweep_instances]
+    res = {}
+    for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted")):
+        sims = []
+        for k, (G, tau) in enumerate(pairs):
+            s = lbm.Simulation(256, 256, G, tau, storage, 0.5 if storage else 0.0)
+            s.init_droplets(inputs.single_droplet(256, 40), seed=k)
+            sims.append(s)
+        batch = lbm.Batch(sims, steps_per_graph=args.graph_steps)
+        batch.step(args.graph_steps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record()
+        batch.step(args.sweep_steps)
+        e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = e0.elapsed_time(e1)
+        batch.close()
+        unstable = sum(1 for s in sims if not s.metrics()["finite"])
+        lu = 256.0 * 256 * len(sims) * args.sweep_steps
+        bpu = BYTES_F32 if storage == lbm.LBM_F32 else BYTES_F16
+        res[name] = {"mlups": lu / wall / 1e6, "gpu_mlups": lu / (ms * 1e-3) / 1e6,
+                     "achieved_gbs": lu * bpu / (ms * 1e-3) / 1e9, "instances": len(sims),
+                     "steps": args.sweep_steps, "unstable_instances": unstable}
+        log(f"[sweep {name}] {res[name]['gpu_mlups']:.0f} MLUPS, {unstable} unstable")
+        for s in sims:
+            s.close()
+        del sims
+        torch.cuda.empty_cache()
+    return res
+
+
+def run_serving(args, torch, lbm, inputs):
+    """Poisson trace, continuous batching vs the plain one-at-a-time path."""
+    trace = inputs.serving_trace(args.serve_requests, rate=args.serve_rate, seed=4,
+                                 nmax=args.serve_nmax, smax=args.serve_smax)
+    res = {}
+    for policy, name in ((lbm.LBM_POLICY_CONTINUOUS, "continuous"), (lbm.LBM_POLICY_FIFO, "fifo")):
+        srv = lbm.Server(args.serve_pool_gb << 30, policy=policy, steps_per_tick=args.graph_steps,
+                         max_slots=256)
+        t0 = srv.clock()
+        tickets = []
+        for r in trace:
+            while srv.clock() - t0 < r.arrival:
+                time.sleep(min(0.001, max(0.0, r.arrival - (srv.clock() - t0))))
+            tickets.append(srv.submit(r.n, r.n, r.G, r.tau, r.steps, r.drops, seed=r.seed))
+        srv.drain()
+        lat, done, unstable = [], [], 0
+        for t in tickets:
+            code, m = srv.poll(t)
+            lat.append(m["t_done"] - m["t_submit"])
+            done.append(m["t_done"])
+            unstable += code != lbm.LBM_OK
+        st = srv.stats()
+        srv.close()
+        lat.sort()
+        makespan = max(done) - t0
+        res[name] = {"requests": len(trace), "aggregate_mlups": st["lattice_updates"] / makespan / 1e6,
+                     "p50_ms": 1e3 * lat[len(lat) // 2],
+                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+                     "makespan_s": makespan, "unstable": unstable,
+                     "pool_high_water_gb": st["pool_high_water"] / 2**30}
+        log(f"[serving {name}] {res[name]}")
+        torch.cuda.empty_cache()
+    return res
+
+
+def run_cpu_baseline(args, inputs):
+    """The FP64 oracle on the host cores, on a 512^2 window of the same workload."""
+    import oracle
+    n = 512
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    drops = inputs.many_droplets(args.n, args.drops, 8, 48, seed=3)
+    f = oracle.droplet_state(n, n, drops, seed=3, period=(args.n, args.n))
+    t0 = time.perf_counter()
+    f = oracle.step(f, args.G, args.tau, 20, threads)
+    probe = time.perf_counter() - t0
+    steps = max(20, int(20 * args.cpu_seconds / max(probe, 1e-3)))
+    t0 = time.perf_counter()
+    oracle.step(f, args.G, args.tau, steps, threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"FP64 oracle, {n}x{n} window of the 4096^2 2000-droplet field, {steps} steps, "
+                      f"{dt:.1f} s on {threads} host threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3, help="timed bench steps (whole jobs)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--drops", type=int, default=2000)
+    ap.add_argument("--G", type=float, default=-5.5)
+    ap.add_argument("--tau", type=float, default=1.0)
+    ap.add_argument("--lbm-steps", type=int, default=5000)
+    ap.add_argument("--tile", type=int, default=-1, help="fixed tile shape (default: autotune)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip sweep, serving and CPU baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--graph-steps", type=int, default=32)
+    ap.add_argument("--sweep-instances", type=int, default=512)
+    ap.add_argument("--sweep-steps", type=int, default=4000)
+    ap.add_argument("--serve-requests", type=int, default=64)
+    ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--serve-nmax", type=int, default=2048)
+    ap.add_argument("--serve-smax", type=int, default=20000)
+    ap.add_argument("--serve-pool-gb", type=int, default=32)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2504_10539_amd import inputs, lbm
+
+    log(f"device {torch.cuda.get_device_name(0)}; workload {args.n}^2, {args.drops} droplets, "
+        f"G {args.G}, tau {args.tau}, {args.lbm_steps} LBM steps per job")
+    main_res = run_main(args, torch, lbm, inputs)
+    f32 = main_res["f32"]
+    khash = kernel_source_hash()
+    copy_gbs = run_copy_reference(torch, lbm)
+    traffic = traffic_from_profiles(khash, f"f32_{args.n}")
+    line = {
+        "metric": "MLUPS & % HBM roofline (FP32 vs FP16-shifted); batched p50/p99 latency",
+        "value": round(f32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms_per_job"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"many_droplets_{args.n}", "grid": [args.n, args.n],
+                   "droplets": args.drops, "radius": [8, 48], "G": args.G, "tau": args.tau,
+                   "lbm_steps_per_step": args.lbm_steps, "storage": "f32",
+                   "parallelism": "single_gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(f32["achieved_gbs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(f32["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step<StoreF32>",
+                     "bytes_per_update": BYTES_F32, "launch_ms": round(f32["step_kernel_ms"], 5),
+                     "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
+        "f32": f32,
+    }
+    if "f16_shifted" in main_res:
+        f16 = main_res["f16_shifted"]
+        f16 = dict(f16, roofline_frac=round(f16["achieved_gbs"] / HBM_PEAK_GBS, 4))
+        line["f16_shifted"] = f16
+    if not args.no_extras:
+        line["sweep_512x256"] = run_sweep(args, torch, lbm, inputs)
+        line["serving"] = run_serving(args, torch, lbm, inputs)
+        if not args.no_cpu:
+            line["cpu_baseline"] = run_cpu_baseline(args, inputs)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,162 @@
+// sc_device.h -- device-side types and the per-cell arithmetic of the D2Q9
+// Shan-Chen step (Li & Zhang, arXiv 2504.10539, Sec. II-A, Eq. (1)).
+//
+// One inlined cell update is shared by the single-run and the batched step
+// kernels, so a simulation's result does not depend on which launch path or
+// tile shape advanced it.  The library is compiled with -ffp-contract=off;
+// every fused multiply-add below is written out, which keeps the arithmetic
+// identical in every kernel that inlines it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sclbm {
+
+// D2Q9 weights in FP32 (4/9, 1/9, 1/36).
+constexpr float kW0 = 4.0f / 9.0f;
+constexpr float kW1 = 1.0f / 9.0f;
+constexpr float kW2 = 1.0f / 36.0f;
+
+// Per-simulation record read by the step kernels.  pop[0]/pop[1] are the two
+// population buffers; the state before launch `sub` of a sequence sits in
+// pop[(parity + sub) & 1] and launch `sub` runs only while sub < nsub.
+struct InstDesc {
+  uint64_t pop[2];
+  int32_t nx, ny;
+  float G, tau, omega, rho0;
+  int32_t parity;
+  int32_t nsub;
+  int64_t remaining;  // batched runs: steps still to take
+  int64_t steps;      // batched runs: steps taken
+  int32_t storage;
+  int32_t pad[3];
+};
+static_assert(sizeof(InstDesc) == 80, "InstDesc layout");
+
+// One unit of step-kernel work: rows [y0, y0 + h) of the strip of columns
+// starting at x0 of simulation `inst`.
+struct TileItem {
+  int32_t inst, x0, y0, h;
+};
+
+// ------------------------------------------------------------------ storage
+
+// FP32 populations.
+struct StoreF32 {
+  using T = float;
+  static constexpr int kBytes = 4;
+  template <class P>
+  __device__ static __forceinline__ float load(P p, float /*shift*/) { return *p; }
+  __device__ static __forceinline__ T pack(float v, float /*shift*/) { return v; }
+};
+
+// FP16 populations holding f_i - w_i rho0, widened back to FP32 on load.
+struct StoreF16S {
+  using T = _Float16;
+  static constexpr int kBytes = 2;
+  template <class P>
+  __device__ static __forceinline__ float load(P p, float shift) {
+    return static_cast<float>(*p) + shift;
+  }
+  __device__ static __forceinline__ T pack(float v, float shift) {
+    return static_cast<T>(v - shift);  // v_cvt_f16_f32: round to nearest even
+  }
+};
+
+// Pointer into global memory (address space 1): loads and stores through it
+// use the global_* instructions with a scalar base and a 32-bit lane offset.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(uint64_t a) {
+  return reinterpret_cast<gptr<T>>(a);
+}
+
+__device__ __forceinline__ int wrap_dec(int a, int n) { return a == 0 ? n - 1 : a - 1; }
+__device__ __forceinline__ int wrap_inc(int a, int n) { return a == n - 1 ? 0 : a + 1; }
+
+// ------------------------------------------------------------------ arithmetic
+
+// Density: the populations summed in index order.
+__device__ __forceinline__ float density(const float f[9]) {
+  float r = f[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) r += f[i];
+  return r;
+}
+
+// Pseudopotential psi(rho) = 1 - exp(-rho).
+__device__ __forceinline__ float psi_of(float rho) { return 1.0f - expf(-rho); }
+
+// Interaction force F = -G psi(x) sum_i w_i psi(x + e_i) e_i.  The stencil
+// sum is taken as differences of opposite neighbours first: neighbouring psi
+// values are close, so each difference is exact in FP32 and the sum keeps
+// the antisymmetry of the pair force instead of cancelling large partial
+// sums.
+__device__ __forceinline__ void force_of(float pc, float pE, float pN, float pW, float pS,
+                                         float pNE, float pNW, float pSW, float pSE, float G,
+                                         float& Fx, float& Fy) {
+  const float dA = pNE - pSW;  // e5 against e7
+  const float dB = pSE - pNW;  // e8 against e6
+  const float sx = fmaf(kW1, pE - pW, kW2 * (dA + dB));
+  const float sy = fmaf(kW1, pN - pS, kW2 * (dA - dB));
+  const float gp = -G * pc;
+  Fx = gp * sx;
+  Fy = gp * sy;
+}
+
+// Momentum j = sum_i f_i e_i, as differences of opposite populations.
+__device__ __forceinline__ void momentum(const float f[9], float& jx, float& jy) {
+  const float a = f[5] - f[7];
+  const float b = f[8] - f[6];
+  jx = (f[1] - f[3]) + (a + b);
+  jy = (f[2] - f[4]) + (a - b);
+}
+
+// BGK collision with the Shan-Chen velocity shift, in place on f:
+//   u_eq = (j + tau F) / rho,
+//   f_eq_i = w_i rho (1 + 3 e_i.u + 4.5 (e_i.u)^2 - 1.5 u.u)  (i = 1..8),
+//   f_eq_0 = rho - sum_{i>0} f_eq_i   (mass balance: the rounded weights do
+//                                      not sum to one in FP32),
+//   f*_i = f_i + (f_eq_i - f_i) / tau.
+__device__ __forceinline__ void collide(float f[9], float rho, float Fx, float Fy, float tau,
+                                        float omega) {
+  float jx, jy;
+  momentum(f, jx, jy);
+  const float inv = 1.0f / rho;
+  const float ux = fmaf(tau, Fx, jx) * inv;
+  const float uy = fmaf(tau, Fy, jy) * inv;
+  const float base = fmaf(-1.5f, fmaf(ux, ux, uy * uy), 1.0f);
+  const float r1 = kW1 * rho;
+  const float r2 = kW2 * rho;
+  float feq[9];
+  {
+    const float s = fmaf(4.5f * ux, ux, base), t = 3.0f * ux;
+    feq[1] = r1 * (s + t);
+    feq[3] = r1 * (s - t);
+  }
+  {
+    const float s = fmaf(4.5f * uy, uy, base), t = 3.0f * uy;
+    feq[2] = r1 * (s + t);
+    feq[4] = r1 * (s - t);
+  }
+  {
+    const float v = ux + uy;
+    const float s = fmaf(4.5f * v, v, base), t = 3.0f * v;
+    feq[5] = r2 * (s + t);
+    feq[7] = r2 * (s - t);
+  }
+  {
+    const float v = uy - ux;  // e6 = (-1, 1); e8 = -e6
+    const float s = fmaf(4.5f * v, v, base), t = 3.0f * v;
+    feq[6] = r2 * (s + t);
+    feq[8] = r2 * (s - t);
+  }
+  feq[0] = rho - (((feq[1] + feq[3]) + (feq[2] + feq[4])) + ((feq[5] + feq[7]) + (feq[6] + feq[8])));
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = fmaf(omega, feq[i] - f[i], f[i]);
+}
+
+}  // namespace sclbm

@@ -1,0 +1,786 @@
+// sc_kernels.hip -- gfx950 kernels of the D2Q9 Shan-Chen step and its
+// diagnostics (Li & Zhang, arXiv 2504.10539: Sec. II-A Eq. (1); Sec. III-A
+// initial droplet; Sec. II-D Eqs. (9)-(13) and Sec. IV-F Eqs. (14)-(16)).
+//
+// Population buffers are structure of arrays (plane i of nx*ny, x fastest).
+// A buffer holds post-collision values at the cell they leave from, so the
+// pre-collision state is read by pulling: f_i(x, t) = A_i(x - e_i).  One
+// step reads A and writes the other buffer B at the cell itself; the next
+// step swaps the roles.
+
+#include <hip/hip_runtime.h>
+
+#include "sc_device.h"
+#include "sc_launch.h"
+
+namespace sclbm {
+
+// ============================================================== step kernel
+//
+// A workgroup of NT threads owns a strip of SW = NT * CPT columns (thread t
+// holds columns x0 + t + k NT, k < CPT, so every load and store instruction
+// of a wavefront covers consecutive addresses) and marches down `h` rows.
+// Per row it pulls the nine populations of the next row, forms rho and psi,
+// and puts psi in a four-row LDS ring; after one barrier it has psi on the
+// 3x3 neighbourhood of the current row and collides it.  Each population of
+// the strip is read from HBM once; the extra reads are one halo column on
+// each side (two lanes) and one halo row above and below the band.  PF rows
+// of loads are kept in flight ahead of the row being finished.
+
+template <class S, int NT, int CPT>
+struct Strip {
+  using T = typename S::T;
+  static constexpr int SW = NT * CPT;
+
+  gptr<const T> plane[9];
+  gptr<T> out[9];
+  float sh[9];
+  int nx, ny, x0, y0, h, wcols;
+  // Columns of this lane's cells; slot CPT is the halo column (lanes 0, 1).
+  int xc[CPT + 1], xm[CPT + 1], xp[CPT + 1];
+  bool live[CPT + 1];
+  float G, tau, omega;
+
+  __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti,
+                                        int sub) {
+    nx = dp->nx;
+    ny = dp->ny;
+    x0 = ti.x0;
+    y0 = ti.y0;
+    h = ti.h;
+    wcols = min(SW, nx - x0);
+    G = dp->G;
+    tau = dp->tau;
+    omega = dp->omega;
+    const float rho0 = dp->rho0;
+    const int par = (dp->parity + sub) & 1;
+    const uint64_t a = dp->pop[0], b = dp->pop[1];
+    const uint64_t src = par ? b : a, dst = par ? a : b;
+    const uint64_t n = (uint64_t)nx * (uint64_t)ny * sizeof(T);
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      plane[i] = as_global<const T>(src + (uint64_t)i * n);
+      out[i] = as_global<T>(dst + (uint64_t)i * n);
+      sh[i] = ws[i] * rho0;
+    }
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      const int c = t + k * NT;
+      live[k] = c < wcols;
+      const int x = live[k] ? x0 + c : x0;
+      xc[k] = x;
+      xm[k] = wrap_dec(x, nx);
+      xp[k] = wrap_inc(x, nx);
+    }
+    live[CPT] = t < 2;
+    {
+      const int xl = x0 == 0 ? nx - 1 : x0 - 1;
+      const int xr = (x0 + wcols) % nx;
+      const int x = t == 0 ? xl : xr;
+      xc[CPT] = x;
+      xm[CPT] = wrap_dec(x, nx);
+      xp[CPT] = wrap_inc(x, nx);
+    }
+  }
+
+  // Pre-collision populations of row (y0 + j) mod ny for every live slot.
+  __device__ __forceinline__ void pull(int j, float (&f)[CPT + 1][9]) const {
+    int y = y0 + j;
+    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    const uint32_t r0 = (uint32_t)y * (uint32_t)nx;
+    const uint32_t rm = (uint32_t)wrap_dec(y, ny) * (uint32_t)nx;
+    const uint32_t rp = (uint32_t)wrap_inc(y, ny) * (uint32_t)nx;
+#pragma unroll
+    for (int k = 0; k <= CPT; ++k) {
+      if (live[k]) {
+        const uint32_t c = xc[k], m = xm[k], p = xp[k];
+        f[k][0] = S::load(plane[0] + (r0 + c), sh[0]);
+        f[k][1] = S::load(plane[1] + (r0 + m), sh[1]);
+        f[k][2] = S::load(plane[2] + (rm + c), sh[2]);
+        f[k][3] = S::load(plane[3] + (r0 + p), sh[3]);
+        f[k][4] = S::load(plane[4] + (rp + c), sh[4]);
+        f[k][5] = S::load(plane[5] + (rm + m), sh[5]);
+        f[k][6] = S::load(plane[6] + (rm + p), sh[6]);
+        f[k][7] = S::load(plane[7] + (rp + p), sh[7]);
+        f[k][8] = S::load(plane[8] + (rp + m), sh[8]);
+      }
+    }
+  }
+
+  // psi of row j into ring slot (j + 1) & 3 (LDS column index = strip column + 1).
+  __device__ __forceinline__ void publish(int j, const float (&f)[CPT + 1][9],
+                                          float (*ring)[SW + 2]) const {
+    float* row = ring[(j + 1) & 3];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k)
+      if (live[k]) row[t + k * NT + 1] = psi_of(density(f[k]));
+    if (live[CPT]) row[t == 0 ? 0 : wcols + 1] = psi_of(density(f[CPT]));
+  }
+
+  // Collide row r (psi of rows r-1, r, r+1 already in the ring) and store it.
+  __device__ __forceinline__ void finish(int r, float (&f)[CPT + 1][9],
+                                         const float (*ring)[SW + 2]) const {
+    const float* dn = ring[r & 3];
+    const float* md = ring[(r + 1) & 3];
+    const float* up = ring[(r + 2) & 3];
+    const uint32_t row = (uint32_t)(y0 + r) * (uint32_t)nx;
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) {
+      if (!live[k]) continue;
+      const int c = t + k * NT + 1;
+      float Fx, Fy;
+      force_of(md[c], md[c + 1], up[c], md[c - 1], dn[c], up[c + 1], up[c - 1], dn[c - 1],
+               dn[c + 1], G, Fx, Fy);
+      const float rho = density(f[k]);
+      collide(f[k], rho, Fx, Fy, tau, omega);
+      const uint32_t o = row + (uint32_t)xc[k];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) out[i][o] = S::pack(f[k][i], sh[i]);
+    }
+  }
+};
+
+template <class S, int NT, int CPT, int PF>
+__global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
+                                             const TileItem* __restrict__ items,
+                                             const int* __restrict__ nitems_p, int sub) {
+  using St = Strip<S, NT, CPT>;
+  __shared__ float ring[4][St::SW + 2];
+  const int nitems = *nitems_p;
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
+    const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
+    if (sub >= dp->nsub) continue;
+    St s;
+    s.setup(dp, ti, sub);
+    const int h = s.h;
+    if constexpr (PF == 1) {
+      float a[CPT + 1][9], b[CPT + 1][9];
+      s.pull(-1, a);
+      s.publish(-1, a, ring);
+      s.pull(0, a);
+      s.publish(0, a, ring);
+      int r = 0;
+      while (true) {
+        s.pull(r + 1, b);
+        s.publish(r + 1, b, ring);
+        __syncthreads();
+        s.finish(r, a, ring);
+        if (++r >= h) break;
+        s.pull(r + 1, a);
+        s.publish(r + 1, a, ring);
+        __syncthreads();
+        s.finish(r, b, ring);
+        if (++r >= h) break;
+      }
+    } else {
+      float a[CPT + 1][9], b[CPT + 1][9], c[CPT + 1][9];
+      s.pull(-1, a);
+      s.publish(-1, a, ring);
+      s.pull(0, a);
+      s.pull(1, b);
+      s.publish(0, a, ring);
+      int r = 0;
+      // a: row r (published); b: row r + 1 (in flight)
+      while (true) {
+        if (r + 2 <= h) s.pull(r + 2, c);
+        s.publish(r + 1, b, ring);
+        __syncthreads();
+        s.finish(r, a, ring);
+        if (++r >= h) break;
+        if (r + 2 <= h) s.pull(r + 2, a);
+        s.publish(r + 1, c, ring);
+        __syncthreads();
+        s.finish(r, b, ring);
+        if (++r >= h) break;
+        if (r + 2 <= h) s.pull(r + 2, b);
+        s.publish(r + 1, a, ring);
+        __syncthreads();
+        s.finish(r, c, ring);
+        if (++r >= h) break;
+      }
+    }
+    __syncthreads();  // the next item reuses the ring
+  }
+}
+
+// ============================================================== batched ticks
+
+// Start of a graph replay: every simulation takes min(K, remaining) steps.
+__global__ void k_tick_begin(InstDesc* descs, int n, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int64_t rem = descs[i].remaining;
+    descs[i].nsub = (int32_t)(rem < K ? (rem > 0 ? rem : 0) : K);
+  }
+}
+
+// Before a run of replays: every simulation of the batch has `steps` to take.
+__global__ void k_batch_arm(InstDesc* descs, int n, int64_t steps) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    descs[i].remaining = steps;
+    descs[i].nsub = 0;
+  }
+}
+
+// End of a graph replay: account for the steps taken.
+__global__ void k_tick_end(InstDesc* descs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const int32_t s = descs[i].nsub;
+    descs[i].parity = (descs[i].parity + s) & 1;
+    descs[i].remaining -= s;
+    descs[i].steps += s;
+    descs[i].nsub = 0;
+  }
+}
+
+// ============================================================== cell-parallel helpers
+
+// Pre-collision populations at cell (x, y), pulled from a buffer.
+template <class S>
+__device__ __forceinline__ void pull_cell(const typename S::T* src, size_t n, int nx, int ny, int x,
+                                          int y, float rho0, float f[9]) {
+  const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+  const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+  const size_t r0 = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
+  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+  f[0] = S::load(src + 0 * n + r0 + x, ws[0] * rho0);
+  f[1] = S::load(src + 1 * n + r0 + xm, ws[1] * rho0);
+  f[2] = S::load(src + 2 * n + rm + x, ws[2] * rho0);
+  f[3] = S::load(src + 3 * n + r0 + xp, ws[3] * rho0);
+  f[4] = S::load(src + 4 * n + rp + x, ws[4] * rho0);
+  f[5] = S::load(src + 5 * n + rm + xm, ws[5] * rho0);
+  f[6] = S::load(src + 6 * n + rm + xp, ws[6] * rho0);
+  f[7] = S::load(src + 7 * n + rp + xp, ws[7] * rho0);
+  f[8] = S::load(src + 8 * n + rp + xm, ws[8] * rho0);
+}
+
+// Moments, pass 1: rho (FP32, the step kernel's summation order).
+template <class S>
+__global__ __launch_bounds__(256) void k_rho32(const typename S::T* __restrict__ src, int nx,
+                                               int ny, float rho0, float* __restrict__ rho) {
+  const size_t n = (size_t)nx * ny;
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    float f[9];
+    pull_cell<S>(src, n, nx, ny, (int)(c % nx), (int)(c / nx), rho0, f);
+    rho[c] = density(f);
+  }
+}
+
+// Moments, pass 2: u = (j + F / 2) / rho with the step kernel's force.
+template <class S>
+__global__ __launch_bounds__(256) void k_velocity(const typename S::T* __restrict__ src, int nx,
+                                                  int ny, float rho0, float G,
+                                                  const float* __restrict__ rho,
+                                                  float* __restrict__ ux, float* __restrict__ uy) {
+  const size_t n = (size_t)nx * ny;
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % nx), y = (int)(c / nx);
+    const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+    const size_t r0 = (size_t)y * nx, rm = (size_t)wrap_dec(y, ny) * nx,
+                 rp = (size_t)wrap_inc(y, ny) * nx;
+    float Fx, Fy;
+    force_of(psi_of(rho[r0 + x]), psi_of(rho[r0 + xp]), psi_of(rho[rp + x]), psi_of(rho[r0 + xm]),
+             psi_of(rho[rm + x]), psi_of(rho[rp + xp]), psi_of(rho[rp + xm]),
+             psi_of(rho[rm + xm]), psi_of(rho[rm + xp]), G, Fx, Fy);
+    float f[9];
+    pull_cell<S>(src, n, nx, ny, x, y, rho0, f);
+    float jx, jy;
+    momentum(f, jx, jy);
+    const float r = rho[c];
+    if (ux) ux[c] = fmaf(0.5f, Fx, jx) / r;
+    if (uy) uy[c] = fmaf(0.5f, Fy, jy) / r;
+  }
+}
+
+// State export: pulled pre-collision populations as FP32 planes.
+template <class S>
+__global__ __launch_bounds__(256) void k_get_state(const typename S::T* __restrict__ src, int nx,
+                                                   int ny, float rho0, float* __restrict__ f_out) {
+  const size_t n = (size_t)nx * ny;
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    float f[9];
+    pull_cell<S>(src, n, nx, ny, (int)(c % nx), (int)(c / nx), rho0, f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f_out[i * n + c] = f[i];
+  }
+}
+
+// State import: A_i(x) = f_i(x + e_i), so that the next pull returns f.
+template <class S>
+__global__ __launch_bounds__(256) void k_set_state(const float* __restrict__ f_in, int nx, int ny,
+                                                   float rho0, typename S::T* __restrict__ dst) {
+  const size_t n = (size_t)nx * ny;
+  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % nx), y = (int)(c / nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int xs = x + ex[i], ys = y + ey[i];
+      xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+      ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+      dst[i * n + c] = S::pack(f_in[i * n + (size_t)ys * nx + xs], ws[i] * rho0);
+    }
+  }
+}
+
+// ============================================================== initial droplet
+
+// SplitMix64 (Steele, Lea & Flood 2014) as a counter-based generator: the
+// k-th output of the stream seeded with `seed`.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// rho(x) = rho_g + (rho_l - rho_g) max_k s_k(x) + eta(x) in FP64 (see lbm_init).
+// A workgroup covers a 16 x 16 tile of cells.  Droplets are staged through
+// LDS in chunks of 256, keeping only those that can reach the tile: once
+// (r - R) / width >= 20 the factor 1 - tanh rounds to exactly zero in FP64,
+// so a droplet farther than R + 20 width from every cell of the tile (tested
+// against the tile centre and its half-diagonal) leaves max_k s_k unchanged.
+// The maximum does not depend on the order the kept droplets are visited in.
+constexpr int kInitTile = 16;
+
+__global__ __launch_bounds__(256) void k_init_rho(const double* __restrict__ drops, int nd,
+                                                  InitArgs a, double* __restrict__ rho) {
+  __shared__ double sd[256 * 3];
+  __shared__ int near_n;
+  const int tx = threadIdx.x % kInitTile, ty = threadIdx.x / kInitTile;
+  const int ntx = (a.nx + kInitTile - 1) / kInitTile, nty = (a.ny + kInitTile - 1) / kInitTile;
+  const double px = (double)a.period_x, py = (double)a.period_y;
+  const double reach = 0.5 * (kInitTile - 1) * 1.4142135623730951 + 1.0;
+  for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
+    const int bx = (t % ntx) * kInitTile, by = (t / ntx) * kInitTile;
+    const int x = bx + tx, y = by + ty;
+    const bool ok = x < a.nx && y < a.ny;
+    const int64_t gx = a.origin_x + x, gy = a.origin_y + y;
+    const double tcx = (double)(a.origin_x + bx) + 0.5 * (kInitTile - 1);
+    const double tcy = (double)(a.origin_y + by) + 0.5 * (kInitTile - 1);
+    double smax = 0.0;
+    for (int k0 = 0; k0 < nd; k0 += 256) {
+      const int cnt = min(256, nd - k0);
+      __syncthreads();
+      if (threadIdx.x == 0) near_n = 0;
+      __syncthreads();
+      if ((int)threadIdx.x < cnt) {
+        const double cx = drops[(size_t)(k0 + threadIdx.x) * 3 + 0];
+        const double cy = drops[(size_t)(k0 + threadIdx.x) * 3 + 1];
+        const double R = drops[(size_t)(k0 + threadIdx.x) * 3 + 2];
+        double dx = tcx - cx, dy = tcy - cy;
+        dx -= px * floor(dx / px + 0.5);
+        dy -= py * floor(dy / py + 0.5);
+        if (sqrt(dx * dx + dy * dy) - reach < R + 20.0 * a.width) {
+          const int q = atomicAdd(&near_n, 1);
+          sd[3 * q + 0] = cx;
+          sd[3 * q + 1] = cy;
+          sd[3 * q + 2] = R;
+        }
+      }
+      __syncthreads();
+      const int nn = near_n;
+      for (int k = 0; k < nn; ++k) {
+        double dx = (double)gx - sd[3 * k + 0];
+        double dy = (double)gy - sd[3 * k + 1];
+        dx -= px * floor(dx / px + 0.5);
+        dy -= py * floor(dy / py + 0.5);
+        const double r = sqrt(dx * dx + dy * dy);
+        const double arg = (r - sd[3 * k + 2]) / a.width;
+        if (arg < 20.0) {
+          const double s = 0.5 * (1.0 - tanh(arg));
+          if (s > smax) smax = s;
+        }
+      }
+    }
+    if (ok) {
+      const uint64_t gidx = (uint64_t)gy * (uint64_t)a.period_x + (uint64_t)gx;
+      const double u = (double)(splitmix64_at(a.seed, gidx) >> 11) * (1.0 / 9007199254740992.0);
+      const double eta = a.noise_amp * (2.0 * u - 1.0);
+      rho[(size_t)y * a.nx + x] = a.rho_g + (a.rho_l - a.rho_g) * smax + eta;
+    }
+  }
+}
+
+// Fluid at rest, written pull-shifted: A_i(x) = w_i rho(x + e_i).
+template <class S>
+__global__ __launch_bounds__(256) void k_init_pop(const double* __restrict__ rho, int nx, int ny,
+                                                  float rho0, typename S::T* __restrict__ dst) {
+  const size_t n = (size_t)nx * ny;
+  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const double wd[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                        1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % nx), y = (int)(c / nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int xs = x + ex[i], ys = y + ey[i];
+      xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
+      ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
+      const float f = (float)(wd[i] * rho[(size_t)ys * nx + xs]);
+      dst[i * n + c] = S::pack(f, ws[i] * rho0);
+    }
+  }
+}
+
+// ============================================================== FP64 reductions
+
+constexpr int kRedThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Block-wide reduction of NV values with per-value operator (0 sum, 1 max,
+// 2 min), in a fixed order; thread 0 gets the results in v.
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV]) {
+  __shared__ double part[kRedThreads / 64][NV];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    v[q] = op[q] == 0 ? wave_sum(v[q]) : (op[q] == 1 ? wave_max(v[q]) : wave_min(v[q]));
+    if (lane == 0) part[wid][q] = v[q];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double a = part[0][q];
+      for (int w = 1; w < kRedThreads / 64; ++w)
+        a = op[q] == 0 ? a + part[w][q] : (op[q] == 1 ? fmax(a, part[w][q]) : fmin(a, part[w][q]));
+      v[q] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Diagnostics pass 1: rho in FP64 (sum of the widened populations in index
+// order) into a scratch plane, plus mass, momentum and a count of cells that
+// are not finite or have rho <= 0.  Partials per block: [0..3].
+template <class S>
+__global__ __launch_bounds__(kRedThreads) void k_diag_rho(const typename S::T* __restrict__ src,
+                                                          int nx, int ny, float rho0,
+                                                          double* __restrict__ rho64,
+                                                          double* __restrict__ partials) {
+  const size_t n = (size_t)nx * ny;
+  double m = 0.0, px = 0.0, py = 0.0, bad = 0.0;
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    float f[9];
+    pull_cell<S>(src, n, nx, ny, (int)(c % nx), (int)(c / nx), rho0, f);
+    double r = 0.0;
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      r += (double)f[i];
+      fin = fin && isfinite(f[i]);
+    }
+    const double jx = ((double)f[1] - (double)f[3]) + ((double)f[5] - (double)f[6]) +
+                      ((double)f[8] - (double)f[7]);
+    const double jy = ((double)f[2] - (double)f[4]) + ((double)f[5] - (double)f[8]) +
+                      ((double)f[6] - (double)f[7]);
+    rho64[c] = r;
+    m += r;
+    px += jx;
+    py += jy;
+    if (!fin || !(r > 0.0)) bad += 1.0;
+  }
+  double v[4] = {m, px, py, bad};
+  const int op[4] = {0, 0, 0, 0};
+  block_reduce<4>(v, op);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 4; ++q) partials[blockIdx.x * kPartialStride + q] = v[q];
+}
+
+// Diagnostics pass 2: Eq. (16) |grad rho| with periodic wrap, and the sums
+// and extrema of Eqs. (9)-(15).  Partials per block: [4..9].
+__global__ __launch_bounds__(kRedThreads) void k_diag_grad(const double* __restrict__ rho, int nx,
+                                                           int ny, double* __restrict__ partials) {
+  const size_t n = (size_t)nx * ny;
+  double cnt = 0.0, gmax = 0.0, gsum = 0.0, g2 = 0.0, rmax = -INFINITY, rmin = INFINITY;
+  for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
+       c += (size_t)gridDim.x * blockDim.x) {
+    const int x = (int)(c % nx), y = (int)(c / nx);
+    const size_t r0 = (size_t)y * nx;
+    const double gx = (rho[r0 + wrap_inc(x, nx)] - rho[r0 + wrap_dec(x, nx)]) / 2.0;
+    const double gy = (rho[(size_t)wrap_inc(y, ny) * nx + x] - rho[(size_t)wrap_dec(y, ny) * nx + x]) / 2.0;
+    const double g = sqrt(gx * gx + gy * gy);
+    const double r = rho[c];
+    if (g > 0.01) cnt += 1.0;
+    gmax = fmax(gmax, g);
+    gsum += g;
+    g2 += g * g;
+    rmax = fmax(rmax, r);
+    rmin = fmin(rmin, r);
+  }
+  double v[6] = {cnt, gmax, gsum, g2, rmax, rmin};
+  const int op[6] = {0, 1, 0, 0, 1, 2};
+  block_reduce<6>(v, op);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 6; ++q) partials[blockIdx.x * kPartialStride + 4 + q] = v[q];
+}
+
+// Final pass: one block folds the per-block partials in a fixed order.
+__global__ __launch_bounds__(kRedThreads) void k_diag_final(const double* __restrict__ partials,
+                                                            int nblocks, double* __restrict__ out) {
+  const int op10[10] = {0, 0, 0, 0, 0, 1, 0, 0, 1, 2};
+  double v[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) v[q] = op10[q] == 1 ? -INFINITY : (op10[q] == 2 ? INFINITY : 0.0);
+  for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const double p = partials[b * kPartialStride + q];
+      v[q] = op10[q] == 0 ? v[q] + p : (op10[q] == 1 ? fmax(v[q], p) : fmin(v[q], p));
+    }
+  }
+  block_reduce<10>(v, op10);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 10; ++q) out[q] = v[q];
+}
+
+// ============================================================== bandwidth reference
+
+// Streaming copy: each thread moves four 16-byte vectors per round, loads
+// issued before stores.
+__global__ __launch_bounds__(256) void k_copy(const float4* __restrict__ src,
+                                              float4* __restrict__ dst, size_t n) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const float4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n; i += stride) dst[i] = src[i];
+}
+
+// ============================================================== launchers
+
+namespace {
+
+template <class S, int NT, int CPT, int PF>
+hipError_t launch_step_t(const InstDesc* descs, const TileItem* items, const int* nitems,
+                         int grid, int sub, hipStream_t st) {
+  hipLaunchKernelGGL((k_step<S, NT, CPT, PF>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
+                     sub);
+  return hipGetLastError();
+}
+
+template <class S, int NT, int CPT, int PF>
+const void* step_fn_t() {
+  return reinterpret_cast<const void*>(&k_step<S, NT, CPT, PF>);
+}
+
+using StepLauncher = hipError_t (*)(const InstDesc*, const TileItem*, const int*, int, int,
+                                    hipStream_t);
+using StepFn = const void* (*)();
+
+#define SCLBM_VARIANT(NT, CPT, PF) {NT, CPT, PF}
+constexpr StepVariant kVariants[] = {
+    SCLBM_VARIANT(64, 1, 1),  SCLBM_VARIANT(64, 1, 2),  SCLBM_VARIANT(128, 1, 1),
+    SCLBM_VARIANT(128, 1, 2), SCLBM_VARIANT(64, 4, 1),  SCLBM_VARIANT(128, 2, 1),
+    SCLBM_VARIANT(128, 2, 2), SCLBM_VARIANT(256, 1, 1), SCLBM_VARIANT(256, 1, 2),
+    SCLBM_VARIANT(256, 2, 1), SCLBM_VARIANT(512, 1, 1),
+};
+#undef SCLBM_VARIANT
+
+template <class S>
+constexpr StepLauncher kLaunch[] = {
+    launch_step_t<S, 64, 1, 1>,  launch_step_t<S, 64, 1, 2>,  launch_step_t<S, 128, 1, 1>,
+    launch_step_t<S, 128, 1, 2>, launch_step_t<S, 64, 4, 1>,  launch_step_t<S, 128, 2, 1>,
+    launch_step_t<S, 128, 2, 2>, launch_step_t<S, 256, 1, 1>, launch_step_t<S, 256, 1, 2>,
+    launch_step_t<S, 256, 2, 1>, launch_step_t<S, 512, 1, 1>,
+};
+
+template <class S>
+constexpr StepFn kFn[] = {
+    step_fn_t<S, 64, 1, 1>,  step_fn_t<S, 64, 1, 2>,  step_fn_t<S, 128, 1, 1>,
+    step_fn_t<S, 128, 1, 2>, step_fn_t<S, 64, 4, 1>,  step_fn_t<S, 128, 2, 1>,
+    step_fn_t<S, 128, 2, 2>, step_fn_t<S, 256, 1, 1>, step_fn_t<S, 256, 1, 2>,
+    step_fn_t<S, 256, 2, 1>, step_fn_t<S, 512, 1, 1>,
+};
+
+static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
+
+int grid_for(size_t n, int threads, int cap) {
+  size_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  if (g > (size_t)cap) g = cap;
+  return (int)g;
+}
+
+}  // namespace
+
+const StepVariant& step_variant(int v) { return kVariants[v]; }
+
+hipError_t launch_step(int storage, int variant, const InstDesc* descs, const TileItem* items,
+                       const int* nitems, int grid, int sub, hipStream_t st) {
+  if (storage == 0) return kLaunch<StoreF32>[variant](descs, items, nitems, grid, sub, st);
+  return kLaunch<StoreF16S>[variant](descs, items, nitems, grid, sub, st);
+}
+
+hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu) {
+  const void* fn = storage == 0 ? kFn<StoreF32>[variant]() : kFn<StoreF16S>[variant]();
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn,
+                                                      kVariants[variant].threads, 0);
+}
+
+hipError_t launch_tick_begin(InstDesc* descs, int n, int K, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick_begin, dim3((n + 255) / 256), dim3(256), 0, st, descs, n, K);
+  return hipGetLastError();
+}
+
+hipError_t launch_tick_end(InstDesc* descs, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_tick_end, dim3((n + 255) / 256), dim3(256), 0, st, descs, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t st) {
+  hipLaunchKernelGGL(k_batch_arm, dim3((n + 255) / 256), dim3(256), 0, st, descs, n, steps);
+  return hipGetLastError();
+}
+
+hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t nd,
+                          int storage, int variant, const InstDesc* descs, const TileItem* items,
+                          const int* nitems, int grid, int sub) {
+  void* args[] = {(void*)&descs, (void*)&items, (void*)&nitems, (void*)&sub};
+  hipKernelNodeParams kp{};
+  kp.func = const_cast<void*>(storage == 0 ? kFn<StoreF32>[variant]() : kFn<StoreF16S>[variant]());
+  kp.gridDim = dim3(grid);
+  kp.blockDim = dim3(kVariants[variant].threads);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(node, g, deps, nd, &kp);
+}
+
+hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps,
+                          size_t nd, bool begin, InstDesc* descs, int n, int K) {
+  hipKernelNodeParams kp{};
+  void* args_b[] = {(void*)&descs, (void*)&n, (void*)&K};
+  void* args_e[] = {(void*)&descs, (void*)&n};
+  kp.func = begin ? reinterpret_cast<void*>(&k_tick_begin) : reinterpret_cast<void*>(&k_tick_end);
+  kp.gridDim = dim3((n + 255) / 256);
+  kp.blockDim = dim3(256);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = begin ? args_b : args_e;
+  kp.extra = nullptr;
+  return hipGraphAddKernelNode(node, g, deps, nd, &kp);
+}
+
+hipError_t launch_moments(int storage, const void* src, int nx, int ny, float rho0, float G,
+                          float* rho, float* ux, float* uy, hipStream_t st) {
+  const size_t n = (size_t)nx * ny;
+  const int g = grid_for(n, 256, 8192);
+  if (storage == 0) {
+    hipLaunchKernelGGL(k_rho32<StoreF32>, dim3(g), dim3(256), 0, st, (const float*)src, nx, ny,
+                       rho0, rho);
+    if (ux || uy)
+      hipLaunchKernelGGL(k_velocity<StoreF32>, dim3(g), dim3(256), 0, st, (const float*)src, nx,
+                         ny, rho0, G, (const float*)rho, ux, uy);
+  } else {
+    hipLaunchKernelGGL(k_rho32<StoreF16S>, dim3(g), dim3(256), 0, st, (const _Float16*)src, nx,
+                       ny, rho0, rho);
+    if (ux || uy)
+      hipLaunchKernelGGL(k_velocity<StoreF16S>, dim3(g), dim3(256), 0, st, (const _Float16*)src,
+                         nx, ny, rho0, G, (const float*)rho, ux, uy);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_get_state(int storage, const void* src, int nx, int ny, float rho0, float* f,
+                            hipStream_t st) {
+  const int g = grid_for((size_t)nx * ny, 256, 8192);
+  if (storage == 0)
+    hipLaunchKernelGGL(k_get_state<StoreF32>, dim3(g), dim3(256), 0, st, (const float*)src, nx,
+                       ny, rho0, f);
+  else
+    hipLaunchKernelGGL(k_get_state<StoreF16S>, dim3(g), dim3(256), 0, st, (const _Float16*)src,
+                       nx, ny, rho0, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_state(int storage, const float* f, int nx, int ny, float rho0, void* dst,
+                            hipStream_t st) {
+  const int g = grid_for((size_t)nx * ny, 256, 8192);
+  if (storage == 0)
+    hipLaunchKernelGGL(k_set_state<StoreF32>, dim3(g), dim3(256), 0, st, f, nx, ny, rho0,
+                       (float*)dst);
+  else
+    hipLaunchKernelGGL(k_set_state<StoreF16S>, dim3(g), dim3(256), 0, st, f, nx, ny, rho0,
+                       (_Float16*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs& a, double* rho64,
+                       float rho0, void* dst, hipStream_t st) {
+  const size_t n = (size_t)a.nx * a.ny;
+  const size_t tiles = (size_t)((a.nx + kInitTile - 1) / kInitTile) * ((a.ny + kInitTile - 1) / kInitTile);
+  const int g = (int)std::min<size_t>(tiles, 16384);
+  hipLaunchKernelGGL(k_init_rho, dim3(g), dim3(256), 0, st, drops, nd, a, rho64);
+  const int g2 = grid_for(n, 256, 8192);
+  if (storage == 0)
+    hipLaunchKernelGGL(k_init_pop<StoreF32>, dim3(g2), dim3(256), 0, st, (const double*)rho64,
+                       a.nx, a.ny, rho0, (float*)dst);
+  else
+    hipLaunchKernelGGL(k_init_pop<StoreF16S>, dim3(g2), dim3(256), 0, st, (const double*)rho64,
+                       a.nx, a.ny, rho0, (_Float16*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, float rho0,
+                              double* rho64, double* partials, double* out, hipStream_t st) {
+  const int g = grid_for((size_t)nx * ny, kRedThreads, kMaxPartials);
+  if (storage == 0)
+    hipLaunchKernelGGL(k_diag_rho<StoreF32>, dim3(g), dim3(kRedThreads), 0, st, (const float*)src,
+                       nx, ny, rho0, rho64, partials);
+  else
+    hipLaunchKernelGGL(k_diag_rho<StoreF16S>, dim3(g), dim3(kRedThreads), 0, st,
+                       (const _Float16*)src, nx, ny, rho0, rho64, partials);
+  hipLaunchKernelGGL(k_diag_grad, dim3(g), dim3(kRedThreads), 0, st, (const double*)rho64, nx, ny,
+                     partials);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, g,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n, 256 * 4, 8192)), dim3(256), 0, st,
+                     (const float4*)src, (float4*)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace sclbm

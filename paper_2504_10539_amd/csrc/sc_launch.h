@@ -1,0 +1,56 @@
+// sc_launch.h -- host-side launchers of the gfx950 kernels (internal to the
+// library; the public boundary is include/lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sc_device.h"
+
+namespace sclbm {
+
+// Step-kernel variants: NT threads per workgroup, CPT cells per thread (strip
+// width NT * CPT), PF rows of loads in flight.
+struct StepVariant {
+  int threads, cells, prefetch;
+};
+constexpr int kNumVariants = 11;
+// Band heights a tile shape may use; tile shape k = variant * kNumRows + row index.
+constexpr int kRowChoices[] = {8, 16, 32, 64, 128};
+constexpr int kNumRows = 5;
+constexpr int kNumTiles = kNumVariants * kNumRows;
+constexpr int kMinStripWidth = 64;
+constexpr int kMinRows = 8;
+
+// Reductions: at most kMaxPartials blocks, kPartialStride doubles each.
+constexpr int kMaxPartials = 2048;
+constexpr int kPartialStride = 16;
+
+struct InitArgs {
+  int nx, ny;
+  double rho_l, rho_g, width, noise_amp;
+  uint64_t seed;
+  int64_t period_x, period_y, origin_x, origin_y;
+};
+
+const StepVariant& step_variant(int v);
+
+hipError_t launch_step(int storage, int variant, const InstDesc* descs, const TileItem* items,
+                       const int* nitems, int grid, int sub, hipStream_t st);
+hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu);
+hipError_t launch_tick_begin(InstDesc* descs, int n, int K, hipStream_t st);
+hipError_t launch_tick_end(InstDesc* descs, int n, hipStream_t st);
+hipError_t launch_moments(int storage, const void* src, int nx, int ny, float rho0, float G,
+                          float* rho, float* ux, float* uy, hipStream_t st);
+hipError_t launch_get_state(int storage, const void* src, int nx, int ny, float rho0, float* f,
+                            hipStream_t st);
+hipError_t launch_set_state(int storage, const float* f, int nx, int ny, float rho0, void* dst,
+                            hipStream_t st);
+hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs& a, double* rho64,
+                       float rho0, void* dst, hipStream_t st);
+// Writes {mass, mom_x, mom_y, bad, n_above, Gmax, sum_grad, sum_grad2, rho_max, rho_min} to out.
+hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, float rho0,
+                              double* rho64, double* partials, double* out, hipStream_t st);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
+
+}  // namespace sclbm

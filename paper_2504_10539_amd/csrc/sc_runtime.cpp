@@ -1,0 +1,759 @@
+// sc_runtime.cpp -- host runtime of the D2Q9 Shan-Chen library: single runs,
+// tile shapes and their autotuner, batched runs over a HIP graph, and the
+// C-ABI entry points declared in include/lbm.h (method: Li & Zhang, arXiv
+// 2504.10539, Sec. II-A Eq. (1), Sec. III-A set-up, Eqs. (9)-(16) metrics).
+#include "sc_runtime.h"
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace sclbm {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_error;
+
+void set_error(const std::string& msg) { g_error = msg; }
+
+lbm_status fail(lbm_status code, const std::string& msg) {
+  g_error = msg;
+  return code;
+}
+
+lbm_status hip_fail(hipError_t e, const char* what) {
+  g_error = std::string(what) + ": " + hipGetErrorString(e);
+  return LBM_EDEVICE;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+lbm_status validate_params(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nx > 65536 || p->ny > 65536)
+    return fail(LBM_EINVAL, "nx and ny must be in [1, 65536]");
+  if ((uint64_t)p->nx * (uint64_t)p->ny * 9ull >= (1ull << 32))
+    return fail(LBM_EINVAL, "grid too large (9 nx ny must be < 2^32)");
+  if (!std::isfinite(p->G)) return fail(LBM_EINVAL, "G must be finite");
+  if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
+  if (p->storage != LBM_F32 && p->storage != LBM_F16_SHIFTED)
+    return fail(LBM_EINVAL, "storage must be LBM_F32 or LBM_F16_SHIFTED");
+  if (p->storage == LBM_F16_SHIFTED && (!std::isfinite(p->rho0) || p->rho0 < 0.0))
+    return fail(LBM_EINVAL, "rho0 must be finite and >= 0");
+  return LBM_OK;
+}
+
+size_t pop_bytes_for(const lbm_params& p) {
+  return 9ull * (size_t)p.nx * (size_t)p.ny * (p.storage == LBM_F32 ? 4 : 2);
+}
+
+WorkLayout work_layout(int nx, int ny) {
+  WorkLayout w{};
+  w.max_items = ((nx + kMinStripWidth - 1) / kMinStripWidth) * ((ny + kMinRows - 1) / kMinRows);
+  size_t o = 0;
+  w.desc = o;
+  o += 256;
+  w.nitems = o;
+  o += 256;
+  w.items = o;
+  o = align_up(o + (size_t)w.max_items * sizeof(TileItem), 256);
+  w.partials = o;
+  o += (size_t)kMaxPartials * kPartialStride * sizeof(double);
+  w.result = o;
+  o += 256;
+  w.total = o;
+  return w;
+}
+
+void make_items(int nx, int ny, int tile, int inst, std::vector<TileItem>& out) {
+  const int sw = tile_width(tile), rows = tile_rows(tile);
+  for (int y0 = 0; y0 < ny; y0 += rows)
+    for (int x0 = 0; x0 < nx; x0 += sw) out.push_back({inst, x0, y0, std::min(rows, ny - y0)});
+}
+
+std::vector<TileItem> xcd_order(const std::vector<TileItem>& items) {
+  const size_t n = items.size();
+  const size_t nx = 8;
+  if (n < 2 * nx) return items;
+  const size_t chunk = (n + nx - 1) / nx;
+  std::vector<TileItem> out;
+  out.reserve(n);
+  for (size_t local = 0; local < chunk; ++local)
+    for (size_t k = 0; k < nx; ++k) {
+      const size_t src = k * chunk + local;
+      if (local < chunk && src < std::min(n, (k + 1) * chunk)) out.push_back(items[src]);
+    }
+  return out;
+}
+
+int default_tile(const lbm_params& p) {
+  // variant index * kNumRows + row index; see kVariants / kRowChoices.
+  if (p.nx <= 64) return 0 * kNumRows + 0;   // 64 threads, 1 cell, 8 rows
+  if (p.nx <= 128) return 2 * kNumRows + 1;  // 128 threads, 16 rows
+  if (p.nx <= 512) return 7 * kNumRows + 2;  // 256 threads, 32 rows
+  return 10 * kNumRows + 3;                  // 512 threads, 64 rows
+}
+
+std::string device_arch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int device_cu_count() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 256;
+  return cus > 0 ? cus : 256;
+}
+
+// ------------------------------------------------------------------ tuning cache
+// JSON Lines, one object per (arch, storage, log2-size bucket of nx and ny).
+
+static std::mutex g_tune_mu;
+
+static int size_bucket(int n) {
+  int b = 0;
+  while ((1 << b) < n) ++b;
+  return b;
+}
+
+struct TuneEntry {
+  std::string arch;
+  int storage, bx, by, tile;
+  double ms;
+};
+
+static std::vector<TuneEntry> read_tune_cache(const char* path) {
+  std::vector<TuneEntry> v;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    char arch[64] = {0};
+    TuneEntry e{};
+    if (sscanf(line.c_str(),
+               "{\"arch\": \"%63[^\"]\", \"storage\": %d, \"bx\": %d, \"by\": %d, \"tile\": %d, "
+               "\"ms\": %lf}",
+               arch, &e.storage, &e.bx, &e.by, &e.tile, &e.ms) == 6 &&
+        e.tile >= 0 && e.tile < kNumTiles) {
+      e.arch = arch;
+      v.push_back(e);
+    }
+  }
+  return v;
+}
+
+int tuned_tile(const lbm_params& p, const std::string& arch) {
+  const char* path = getenv("SCLBM_TUNE_CACHE");
+  if (!path || !*path) return -1;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int bx = size_bucket(p.nx), by = size_bucket(p.ny);
+  for (const TuneEntry& e : read_tune_cache(path))
+    if (e.arch == arch && e.storage == p.storage && e.bx == bx && e.by == by) return e.tile;
+  return -1;
+}
+
+void record_tuned_tile(const lbm_params& p, const std::string& arch, int tile, double ms) {
+  const char* path = getenv("SCLBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  std::vector<TuneEntry> v = read_tune_cache(path);
+  const int bx = size_bucket(p.nx), by = size_bucket(p.ny);
+  v.erase(std::remove_if(v.begin(), v.end(),
+                         [&](const TuneEntry& e) {
+                           return e.arch == arch && e.storage == p.storage && e.bx == bx &&
+                                  e.by == by;
+                         }),
+          v.end());
+  v.push_back({arch, p.storage, bx, by, tile, ms});
+  const std::string tmp = std::string(path) + ".tmp";
+  {
+    std::ofstream out(tmp, std::ios::trunc);
+    for (const TuneEntry& e : v) {
+      char buf[256];
+      snprintf(buf, sizeof buf,
+               "{\"arch\": \"%s\", \"storage\": %d, \"bx\": %d, \"by\": %d, \"tile\": %d, "
+               "\"ms\": %.6f}\n",
+               e.arch.c_str(), e.storage, e.bx, e.by, e.tile, e.ms);
+      out << buf;
+    }
+  }
+  std::rename(tmp.c_str(), path);
+}
+
+}  // namespace sclbm
+
+using namespace sclbm;
+
+// ------------------------------------------------------------------ lbm_ctx
+
+InstDesc lbm_ctx::host_desc() const {
+  InstDesc d{};
+  d.pop[0] = reinterpret_cast<uint64_t>(pop[0]);
+  d.pop[1] = reinterpret_cast<uint64_t>(pop[1]);
+  d.nx = p.nx;
+  d.ny = p.ny;
+  d.G = (float)p.G;
+  d.tau = (float)p.tau;
+  d.omega = (float)(1.0 / p.tau);
+  d.rho0 = p.storage == LBM_F16_SHIFTED ? (float)p.rho0 : 0.0f;
+  d.parity = 0;
+  d.nsub = INT32_MAX;
+  d.storage = p.storage;
+  return d;
+}
+
+lbm_status lbm_ctx::upload_tile(int k) {
+  std::vector<TileItem> items;
+  make_items(p.nx, p.ny, k, 0, items);
+  items = xcd_order(items);
+  if ((int)items.size() > lay.max_items) return fail(LBM_EINVAL, "tile table overflow");
+  const int n = (int)items.size();
+  SCLBM_HIP(hipMemcpyAsync(d_items, items.data(), items.size() * sizeof(TileItem),
+                           hipMemcpyHostToDevice, stream));
+  SCLBM_HIP(hipMemcpyAsync(d_nitems, &n, sizeof(int), hipMemcpyHostToDevice, stream));
+  SCLBM_HIP(hipStreamSynchronize(stream));
+  tile = k;
+  nitems = n;
+  return LBM_OK;
+}
+
+lbm_status lbm_ctx::diagnostics(lbm_metrics* out) {
+  if (!h_result)
+    SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_result), 16 * sizeof(double),
+                            hipHostMallocDefault));
+  void* idle = pop[parity ^ 1];
+  SCLBM_HIP(launch_diagnostics(p.storage, pop[parity], p.nx, p.ny, host_desc().rho0,
+                               reinterpret_cast<double*>(idle), d_partials, d_result, stream));
+  SCLBM_HIP(hipMemcpyAsync(h_result, d_result, 10 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  SCLBM_HIP(hipStreamSynchronize(stream));
+  const double ncell = (double)p.nx * (double)p.ny;
+  const double* r = h_result;
+  lbm_metrics m{};
+  m.mass = r[0];
+  m.mom_x = r[1];
+  m.mom_y = r[2];
+  m.finite = r[3] == 0.0 ? 1 : 0;
+  m.n_above = (int64_t)r[4];
+  m.Gmax = r[5];
+  m.sum_grad = r[6];
+  m.E_int = r[7];
+  m.rho_max = r[8];
+  m.rho_min = r[9];
+  m.W = r[4] / ncell;
+  m.drho = r[8] - r[9];
+  m.W_eff = r[5] > 0.0 ? r[6] / (r[5] * ncell) : 0.0;
+  m.step = steps;
+  *out = m;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batch engine
+
+namespace sclbm {
+hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t nd,
+                          int storage, int variant, const InstDesc* descs, const TileItem* items,
+                          const int* nitems, int grid, int sub);
+hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps,
+                          size_t nd, bool begin, InstDesc* descs, int n, int K);
+hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t st);
+
+size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[2]) {
+  size_t o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
+  for (int s = 0; s < 2; ++s) o += 256 + align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
+  return o;
+}
+
+lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
+                             const int cap_items_[2], const int variants[2], void* work,
+                             size_t wbytes) {
+  stream = st;
+  K = steps_per_tick;
+  cap_inst = cap_inst_;
+  if (wbytes < work_bytes(cap_inst, cap_items_)) return fail(LBM_ENOMEM, "batch workspace too small");
+  char* w = reinterpret_cast<char*>(work);
+  size_t o = 0;
+  d_desc = reinterpret_cast<InstDesc*>(w);
+  o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
+  const int cus = device_cu_count();
+  for (int s = 0; s < 2; ++s) {
+    cap_items[s] = cap_items_[s];
+    variant[s] = variants[s];
+    d_nitems[s] = reinterpret_cast<int*>(w + o);
+    o += 256;
+    d_items[s] = reinterpret_cast<TileItem*>(w + o);
+    o += align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
+    grid[s] = 0;
+    if (variant[s] < 0 || cap_items[s] == 0) continue;
+    int occ = 0;
+    SCLBM_HIP(step_occupancy(s, variant[s], &occ));
+    const int cap = std::max(8, std::max(occ, 1) * cus / 8 * 8);
+    grid[s] = std::min(cap_items[s], cap);
+  }
+  SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc), (size_t)cap_inst * sizeof(InstDesc),
+                          hipHostMallocDefault));
+  for (int s = 0; s < 2; ++s)
+    if (cap_items[s] > 0)
+      SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_items[s]),
+                              (size_t)cap_items[s] * sizeof(TileItem) + 64,
+                              hipHostMallocDefault));
+  SCLBM_HIP(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+  // Graph: tick_begin -> K x (one persistent step launch per storage type) -> tick_end.
+  SCLBM_HIP(hipGraphCreate(&graph, 0));
+  hipGraphNode_t prev;
+  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K));
+  for (int j = 0; j < K; ++j)
+    for (int s = 0; s < 2; ++s) {
+      if (grid[s] == 0) continue;
+      hipGraphNode_t node;
+      SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, variant[s], d_desc, d_items[s],
+                               d_nitems[s], grid[s], j));
+      prev = node;
+    }
+  hipGraphNode_t last;
+  SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K));
+  SCLBM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  return LBM_OK;
+}
+
+lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining) {
+  if ((int)m.size() > cap_inst) return fail(LBM_EINVAL, "too many batch members");
+  // The staging buffers may still feed the previous upload.
+  if (staged_pending) SCLBM_HIP(hipEventSynchronize(staged));
+  int count[2] = {0, 0};
+  for (int i = 0; i < cap_inst; ++i) {
+    InstDesc d{};
+    d.nsub = 0;
+    if (i < (int)m.size()) {
+      lbm_ctx* c = m[i];
+      d = c->host_desc();
+      d.parity = c->parity;
+      d.nsub = 0;
+      d.remaining = remaining[i];
+      d.steps = c->steps;
+      const int s = c->p.storage;
+      if (grid[s] == 0) return fail(LBM_EINVAL, "batch has no kernel for this storage type");
+      std::vector<TileItem> items;
+      make_items(c->p.nx, c->p.ny, variant[s] * kNumRows + (c->tile % kNumRows), i, items);
+      if (count[s] + (int)items.size() > cap_items[s])
+        return fail(LBM_ENOMEM, "batch tile table full");
+      std::copy(items.begin(), items.end(), h_items[s] + count[s]);
+      count[s] += (int)items.size();
+    }
+    h_desc[i] = d;
+  }
+  SCLBM_HIP(hipMemcpyAsync(d_desc, h_desc, (size_t)cap_inst * sizeof(InstDesc),
+                           hipMemcpyHostToDevice, stream));
+  for (int s = 0; s < 2; ++s) {
+    if (cap_items[s] == 0) continue;
+    std::vector<TileItem> v(h_items[s], h_items[s] + count[s]);
+    v = xcd_order(v);
+    std::copy(v.begin(), v.end(), h_items[s]);
+    int* hn = reinterpret_cast<int*>(h_items[s] + cap_items[s]);
+    *hn = count[s];
+    nitems[s] = count[s];
+    if (count[s] > 0)
+      SCLBM_HIP(hipMemcpyAsync(d_items[s], h_items[s], (size_t)count[s] * sizeof(TileItem),
+                               hipMemcpyHostToDevice, stream));
+    SCLBM_HIP(hipMemcpyAsync(d_nitems[s], hn, sizeof(int), hipMemcpyHostToDevice, stream));
+  }
+  SCLBM_HIP(hipEventRecord(staged, stream));
+  staged_pending = true;
+  members = m;
+  return LBM_OK;
+}
+
+lbm_status BatchEngine::arm(int64_t steps) {
+  SCLBM_HIP(launch_batch_arm(d_desc, (int)members.size(), steps, stream));
+  return LBM_OK;
+}
+
+lbm_status BatchEngine::replay() {
+  SCLBM_HIP(hipGraphLaunch(exec, stream));
+  return LBM_OK;
+}
+
+void BatchEngine::destroy() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (staged) (void)hipEventDestroy(staged);
+  if (h_desc) (void)hipHostFree(h_desc);
+  for (int s = 0; s < 2; ++s)
+    if (h_items[s]) (void)hipHostFree(h_items[s]);
+  exec = nullptr;
+  graph = nullptr;
+  staged = nullptr;
+  h_desc = nullptr;
+  h_items[0] = h_items[1] = nullptr;
+}
+
+// Strip variant used for one storage type: that of the widest member's tile.
+int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
+  int best = -1, bestn = -1;
+  for (lbm_ctx* c : m)
+    if (c->p.storage == storage && c->p.nx > bestn) {
+      bestn = c->p.nx;
+      best = tile_variant(c->tile);
+    }
+  return best;
+}
+
+int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant) {
+  int n = 0;
+  for (lbm_ctx* c : m) {
+    if (c->p.storage != storage) continue;
+    std::vector<TileItem> items;
+    make_items(c->p.nx, c->p.ny, variant * kNumRows + (c->tile % kNumRows), 0, items);
+    n += (int)items.size();
+  }
+  return n;
+}
+
+}  // namespace sclbm
+
+struct lbm_batch {
+  std::vector<lbm_ctx*> members;
+  BatchEngine eng;
+};
+
+namespace {
+
+struct BatchShape {
+  int variants[2];
+  int items[2];
+};
+
+BatchShape batch_shape(const std::vector<lbm_ctx*>& m) {
+  BatchShape b{};
+  for (int s = 0; s < 2; ++s) {
+    b.variants[s] = pick_variant(m, s);
+    b.items[s] = b.variants[s] < 0 ? 0 : count_items(m, s, b.variants[s]);
+  }
+  return b;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C-ABI
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_error.c_str(); }
+
+const char* lbm_version(void) { return "sclbm 0.1 (gfx950)"; }
+
+lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes) {
+  const lbm_status s = validate_params(p);
+  if (s != LBM_OK) return s;
+  if (pop_bytes) *pop_bytes = pop_bytes_for(*p);
+  if (work_bytes) *work_bytes = work_layout(p->nx, p->ny).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_bytes, void* work,
+                      size_t work_bytes, void* hip_stream, lbm_ctx** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status s = validate_params(p);
+  if (s != LBM_OK) return s;
+  if (!popA || !popB || !work) return fail(LBM_EINVAL, "buffer pointer is NULL");
+  if (popA == popB) return fail(LBM_EINVAL, "popA and popB must be distinct buffers");
+  if (((uintptr_t)popA | (uintptr_t)popB | (uintptr_t)work) & 255)
+    return fail(LBM_EINVAL, "buffers must be 256-byte aligned");
+  const WorkLayout lay = work_layout(p->nx, p->ny);
+  if (pop_bytes < pop_bytes_for(*p)) return fail(LBM_ENOMEM, "population buffers too small");
+  if (work_bytes < lay.total) return fail(LBM_ENOMEM, "workspace too small");
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return fail(LBM_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->pop[0] = popA;
+  c->pop[1] = popB;
+  c->pop_bytes = pop_bytes;
+  c->work = work;
+  c->work_bytes = work_bytes;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->lay = lay;
+  char* w = reinterpret_cast<char*>(work);
+  c->d_desc = reinterpret_cast<InstDesc*>(w + lay.desc);
+  c->d_nitems = reinterpret_cast<int*>(w + lay.nitems);
+  c->d_items = reinterpret_cast<TileItem*>(w + lay.items);
+  c->d_partials = reinterpret_cast<double*>(w + lay.partials);
+  c->d_result = reinterpret_cast<double*>(w + lay.result);
+  c->arch = device_arch();
+  const InstDesc d = c->host_desc();
+  hipError_t e = hipMemcpyAsync(c->d_desc, &d, sizeof d, hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(e, "descriptor upload");
+  }
+  int k = tuned_tile(*p, c->arch);
+  if (k < 0) k = default_tile(*p);
+  s = c->upload_tile(k);
+  if (s != LBM_OK) {
+    delete c;
+    return s;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (c->h_result) (void)hipHostFree(c->h_result);
+  delete c;
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+lbm_status lbm_init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip) {
+  if (!c || !ip) return fail(LBM_EINVAL, "ctx or init is NULL");
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  if (n < 0 || (n > 0 && !drops)) return fail(LBM_EINVAL, "bad droplet array");
+  const double vals[4] = {ip->rho_l, ip->rho_g, ip->width, ip->noise_amp};
+  for (double v : vals)
+    if (!std::isfinite(v)) return fail(LBM_EINVAL, "init fields must be finite");
+  if (!(ip->width > 0.0) || ip->noise_amp < 0.0)
+    return fail(LBM_EINVAL, "width must be > 0 and noise_amp >= 0");
+  for (int32_t k = 0; k < 3 * n; ++k)
+    if (!std::isfinite(drops[k])) return fail(LBM_EINVAL, "droplet values must be finite");
+  InitArgs a{};
+  a.nx = c->p.nx;
+  a.ny = c->p.ny;
+  a.rho_l = ip->rho_l;
+  a.rho_g = ip->rho_g;
+  a.width = ip->width;
+  a.noise_amp = ip->noise_amp;
+  a.seed = ip->seed;
+  a.period_x = ip->period_x > 0 ? ip->period_x : c->p.nx;
+  a.period_y = ip->period_y > 0 ? ip->period_y : c->p.ny;
+  a.origin_x = ip->origin_x;
+  a.origin_y = ip->origin_y;
+  if (ip->period_x < 0 || ip->period_y < 0 || ip->origin_x < 0 || ip->origin_y < 0)
+    return fail(LBM_EINVAL, "period and origin must be >= 0");
+  if ((ip->period_x == 0 && ip->origin_x != 0) || (ip->period_y == 0 && ip->origin_y != 0))
+    return fail(LBM_EINVAL, "origin requires an explicit period");
+  // Scratch in the second buffer: rho (FP64) then the droplet list.
+  const size_t ncell = (size_t)c->p.nx * c->p.ny;
+  const size_t drop_off = align_up(ncell * sizeof(double), 256);
+  const size_t cap = c->pop_bytes > drop_off ? (c->pop_bytes - drop_off) / (3 * sizeof(double)) : 0;
+  if ((size_t)n > cap)
+    return fail(LBM_EINVAL, "too many droplets for this grid's scratch space (max " +
+                                std::to_string(cap) + ")");
+  char* scratch = reinterpret_cast<char*>(c->pop[1]);
+  double* rho64 = reinterpret_cast<double*>(scratch);
+  double* d_drops = reinterpret_cast<double*>(scratch + drop_off);
+  if (n > 0)
+    SCLBM_HIP(hipMemcpyAsync(d_drops, drops, (size_t)n * 3 * sizeof(double), hipMemcpyHostToDevice,
+                             c->stream));
+  SCLBM_HIP(launch_init(c->p.storage, d_drops, n, a, rho64, c->host_desc().rho0, c->pop[0],
+                        c->stream));
+  SCLBM_HIP(hipStreamSynchronize(c->stream));
+  c->parity = 0;
+  c->steps = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_step_n(lbm_ctx* c, int64_t n) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  const int v = tile_variant(c->tile);
+  for (int64_t j = 0; j < n; ++j) {
+    SCLBM_HIP(launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
+                          c->parity, c->stream));
+    c->parity ^= 1;
+    c->steps += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_moments(lbm_ctx* c, float* rho, float* ux, float* uy) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (!rho && !ux && !uy) return LBM_OK;
+  float* r = rho ? rho : reinterpret_cast<float*>(c->pop[c->parity ^ 1]);
+  SCLBM_HIP(launch_moments(c->p.storage, c->pop[c->parity], c->p.nx, c->p.ny, c->host_desc().rho0,
+                           (float)c->p.G, r, ux, uy, c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_interface_metrics(lbm_ctx* c, lbm_metrics* out) {
+  if (!c || !out) return fail(LBM_EINVAL, "ctx or out is NULL");
+  return c->diagnostics(out);
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, float* f) {
+  if (!c || !f) return fail(LBM_EINVAL, "ctx or buffer is NULL");
+  SCLBM_HIP(launch_get_state(c->p.storage, c->pop[c->parity], c->p.nx, c->p.ny,
+                             c->host_desc().rho0, f, c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const float* f) {
+  if (!c || !f) return fail(LBM_EINVAL, "ctx or buffer is NULL");
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  SCLBM_HIP(launch_set_state(c->p.storage, f, c->p.nx, c->p.ny, c->host_desc().rho0,
+                             c->pop[c->parity], c->stream));
+  return LBM_OK;
+}
+
+int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+int32_t lbm_tile_count(void) { return kNumTiles; }
+
+lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
+                             int32_t* prefetch) {
+  if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+  const StepVariant& v = step_variant(tile_variant(k));
+  if (width) *width = v.threads * v.cells;
+  if (rows) *rows = tile_rows(k);
+  if (threads) *threads = v.threads;
+  if (prefetch) *prefetch = v.prefetch;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  return c->upload_tile(k);
+}
+
+int32_t lbm_get_tile(const lbm_ctx* c) { return c ? c->tile : -1; }
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  SCLBM_HIP(hipEventCreate(&e0));
+  SCLBM_HIP(hipEventCreate(&e1));
+  int best = c->tile;
+  double best_ms = 1e300;
+  lbm_status st = LBM_OK;
+  for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+    st = c->upload_tile(k);
+    if (st != LBM_OK) break;
+    const int v = tile_variant(k);
+    // Read the current buffer and write the idle one, leaving the state as is.
+    hipError_t e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
+                               c->parity, c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+      e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems, c->parity,
+                      c->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "autotune launch");
+      break;
+    }
+    const double per = ms / reps;
+    if (per < best_ms) {
+      best_ms = per;
+      best = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != LBM_OK) return st;
+  st = c->upload_tile(best);
+  if (st != LBM_OK) return st;
+  record_tuned_tile(c->p, c->arch, best, best_ms);
+  if (best_out) *best_out = best;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ batch C-ABI
+
+lbm_status lbm_batch_work_bytes(lbm_ctx* const* ctxs, int32_t n, size_t* bytes) {
+  if (!ctxs || n < 1 || !bytes) return fail(LBM_EINVAL, "bad batch arguments");
+  std::vector<lbm_ctx*> m(ctxs, ctxs + n);
+  for (lbm_ctx* c : m)
+    if (!c) return fail(LBM_EINVAL, "NULL context in batch");
+  const BatchShape b = batch_shape(m);
+  *bytes = BatchEngine::work_bytes(n, b.items);
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* work, size_t work_bytes,
+                            int32_t steps_per_graph, lbm_batch** out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!ctxs || n < 1 || !work) return fail(LBM_EINVAL, "bad batch arguments");
+  if (steps_per_graph < 1 || steps_per_graph > 4096)
+    return fail(LBM_EINVAL, "steps_per_graph must be in [1, 4096]");
+  if ((uintptr_t)work & 255) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+  std::vector<lbm_ctx*> m(ctxs, ctxs + n);
+  for (size_t i = 0; i < m.size(); ++i) {
+    if (!m[i]) return fail(LBM_EINVAL, "NULL context in batch");
+    if (m[i]->batch) return fail(LBM_EBUSY, "context already belongs to a batch");
+    if (m[i]->stream != m[0]->stream) return fail(LBM_EINVAL, "batch members need one stream");
+    for (size_t j = 0; j < i; ++j)
+      if (m[j] == m[i]) return fail(LBM_EINVAL, "context listed twice");
+  }
+  const BatchShape shape = batch_shape(m);
+  lbm_batch* b = new (std::nothrow) lbm_batch();
+  if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+  b->members = m;
+  lbm_status st = b->eng.init(m[0]->stream, steps_per_graph, n, shape.items, shape.variants, work,
+                              work_bytes);
+  if (st == LBM_OK) st = b->eng.load(m, std::vector<int64_t>(m.size(), 0));
+  if (st != LBM_OK) {
+    b->eng.destroy();
+    delete b;
+    return st;
+  }
+  for (lbm_ctx* c : m) c->batch = b;
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_step_n(lbm_batch* b, int64_t n) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  lbm_status st = b->eng.arm(n);
+  const int64_t replays = (n + b->eng.K - 1) / b->eng.K;
+  for (int64_t r = 0; r < replays && st == LBM_OK; ++r) st = b->eng.replay();
+  if (st != LBM_OK) return st;
+  for (lbm_ctx* c : b->members) {
+    c->steps += n;
+    c->parity = (int)((c->parity + n) & 1);
+  }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_destroy(lbm_batch* b) {
+  if (!b) return LBM_OK;
+  const hipError_t e = hipStreamSynchronize(b->eng.stream);
+  for (lbm_ctx* c : b->members) c->batch = nullptr;
+  b->eng.destroy();
+  delete b;
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+lbm_status lbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if (!dst || !src) return fail(LBM_EINVAL, "NULL buffer");
+  if (bytes % 16) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
+  SCLBM_HIP(launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream)));
+  return LBM_OK;
+}
+
+}  // extern "C"

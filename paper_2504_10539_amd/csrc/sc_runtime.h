@@ -1,0 +1,116 @@
+// sc_runtime.h -- host runtime internals shared by the single-run, batch and
+// serving parts of the library (not part of the public ABI, see lbm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "sc_launch.h"
+
+namespace sclbm {
+
+void set_error(const std::string& msg);
+lbm_status fail(lbm_status code, const std::string& msg);
+lbm_status hip_fail(hipError_t e, const char* what);
+
+#define SCLBM_HIP(call)                                     \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return ::sclbm::hip_fail(e_, #call); \
+  } while (0)
+
+lbm_status validate_params(const lbm_params* p);
+size_t pop_bytes_for(const lbm_params& p);
+size_t align_up(size_t v, size_t a);
+
+// Tile shape k -> (variant, rows).
+inline int tile_variant(int k) { return k / kNumRows; }
+inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }
+inline int tile_width(int k) {
+  const StepVariant& v = step_variant(tile_variant(k));
+  return v.threads * v.cells;
+}
+
+// Work items of one grid for tile shape k, appended for simulation `inst`.
+void make_items(int nx, int ny, int tile, int inst, std::vector<TileItem>& out);
+// Reorders items so that the workgroups a hardware XCD receives (workgroup
+// ids congruent mod 8) cover a contiguous run of the original order.
+std::vector<TileItem> xcd_order(const std::vector<TileItem>& items);
+
+// Workspace layout of a single run.
+struct WorkLayout {
+  size_t desc, nitems, items, partials, result, total;
+  int max_items;
+};
+WorkLayout work_layout(int nx, int ny);
+
+int default_tile(const lbm_params& p);
+int tuned_tile(const lbm_params& p, const std::string& arch);  // -1 if none
+void record_tuned_tile(const lbm_params& p, const std::string& arch, int tile, double ms);
+std::string device_arch();
+int device_cu_count();
+
+// Multi-simulation stepping: a device descriptor table and one tile table per
+// storage type, advanced by a HIP graph of K persistent step launches between
+// a tick-begin and a tick-end kernel.  The graph reads the tables from device
+// memory, so members can change between replays without rebuilding it.
+struct BatchEngine {
+  hipStream_t stream = nullptr;
+  int K = 1, cap_inst = 0;
+  int cap_items[2] = {0, 0}, variant[2] = {-1, -1}, grid[2] = {0, 0}, nitems[2] = {0, 0};
+  InstDesc* d_desc = nullptr;
+  int* d_nitems[2] = {nullptr, nullptr};
+  TileItem* d_items[2] = {nullptr, nullptr};
+  InstDesc* h_desc = nullptr;
+  TileItem* h_items[2] = {nullptr, nullptr};
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<lbm_ctx*> members;
+
+  static size_t work_bytes(int cap_inst, const int cap_items[2]);
+  lbm_status init(hipStream_t st, int steps_per_tick, int cap_inst, const int cap_items[2],
+                  const int variants[2], void* work, size_t wbytes);
+  // Uploads the members' descriptors (with `remaining` steps each) and tiles.
+  lbm_status load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining);
+  // Sets every member's remaining steps on the device.
+  lbm_status arm(int64_t steps);
+  // One replay: each member takes min(K, remaining) steps.
+  lbm_status replay();
+  void destroy();
+};
+
+int pick_variant(const std::vector<lbm_ctx*>& m, int storage);
+int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant);
+
+}  // namespace sclbm
+
+struct lbm_ctx {
+  lbm_params p{};
+  void* pop[2] = {nullptr, nullptr};
+  size_t pop_bytes = 0;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  hipStream_t stream = nullptr;
+  int parity = 0;  // buffer holding the current state
+  int64_t steps = 0;
+  int tile = 0;
+  int nitems = 0;
+  sclbm::WorkLayout lay{};
+  sclbm::InstDesc* d_desc = nullptr;
+  int* d_nitems = nullptr;
+  sclbm::TileItem* d_items = nullptr;
+  double* d_partials = nullptr;
+  double* d_result = nullptr;
+  double* h_result = nullptr;  // pinned
+  lbm_batch* batch = nullptr;  // non-null while driven by a batch
+  std::string arch;
+
+  sclbm::InstDesc host_desc() const;
+  lbm_status upload_tile(int k);
+  lbm_status diagnostics(lbm_metrics* out);
+};

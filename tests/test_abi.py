@@ -1,0 +1,105 @@
+"""The C-ABI library loads without a GPU and exports exactly what include/lbm.h declares.
+
+Also checks the ctypes structs against the C layout (a gcc-compiled probe of
+the header) and the argument validation paths that need no device.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:lbm_status|int32_t|int64_t|double|char)\s*\*?\s*"
+                       r"(lbm_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2504_10539_amd import lbm as _lbm
+    return _lbm
+
+
+def test_header_declares_the_boundary():
+    names = header_functions()
+    for required in ("lbm_create", "lbm_init_droplets", "lbm_step_n", "lbm_moments",
+                     "lbm_interface_metrics", "lbm_submit", "lbm_poll"):
+        assert required in names
+    assert len(names) >= 25
+
+
+def test_library_exports_every_declared_symbol(lbm):
+    for name in header_functions():
+        assert hasattr(lbm.LIB, name), name
+
+
+def test_binding_covers_the_header(lbm):
+    assert set(lbm._PROTOS) == set(header_functions())
+
+
+def test_struct_layouts_match_c(lbm, tmp_path):
+    structs = ["lbm_params", "lbm_init", "lbm_metrics", "lbm_server_opts", "lbm_request",
+               "lbm_result", "lbm_server_stats"]
+    src = tmp_path / "probe.c"
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void){"]
+    for s in structs:
+        lines.append(f'printf("{s} %zu\\n", sizeof({s}));')
+    lines.append('printf("lbm_request.steps %zu\\n", offsetof(lbm_request, steps));')
+    lines.append('printf("lbm_request.rho_out %zu\\n", offsetof(lbm_request, rho_out));')
+    lines.append('printf("lbm_metrics.n_above %zu\\n", offsetof(lbm_metrics, n_above));')
+    lines.append('printf("lbm_result.t_done %zu\\n", offsetof(lbm_result, t_done));')
+    lines.append("return 0;}")
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c11", "-Wall", "-Werror", "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    for s in structs:
+        assert ctypes.sizeof(getattr(lbm, s)) == int(out[s]), s
+    assert lbm.lbm_request.steps.offset == int(out["lbm_request.steps"])
+    assert lbm.lbm_request.rho_out.offset == int(out["lbm_request.rho_out"])
+    assert lbm.lbm_metrics.n_above.offset == int(out["lbm_metrics.n_above"])
+    assert lbm.lbm_result.t_done.offset == int(out["lbm_result.t_done"])
+
+
+def test_buffer_sizes_and_validation(lbm):
+    p = lbm.make_params(100, 60, -5.0, 1.0, lbm.LBM_F32)
+    pop, work = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lbm.LIB.lbm_buffer_bytes(ctypes.byref(p), ctypes.byref(pop), ctypes.byref(work)) == 0
+    assert pop.value == 9 * 100 * 60 * 4 and work.value > 0
+    p16 = lbm.make_params(100, 60, -5.0, 1.0, lbm.LBM_F16_SHIFTED, 0.5)
+    assert lbm.LIB.lbm_buffer_bytes(ctypes.byref(p16), ctypes.byref(pop), None) == 0
+    assert pop.value == 9 * 100 * 60 * 2
+    bad = [lbm.make_params(0, 60, -5.0, 1.0), lbm.make_params(10, 10, -5.0, 0.5),
+           lbm.make_params(10, 10, float("nan"), 1.0), lbm.make_params(10, 10, -5.0, 1.0, 7),
+           lbm.make_params(10, 10, -5.0, 1.0, lbm.LBM_F16_SHIFTED, -1.0),
+           lbm.make_params(70000, 10, -5.0, 1.0)]
+    for b in bad:
+        assert lbm.LIB.lbm_buffer_bytes(ctypes.byref(b), ctypes.byref(pop), None) == lbm.LBM_EINVAL
+        assert lbm.last_error()
+    h = ctypes.c_void_p()
+    assert lbm.LIB.lbm_create(ctypes.byref(p), None, None, 0, None, 0, None,
+                              ctypes.byref(h)) == lbm.LBM_EINVAL
+    assert lbm.LIB.lbm_create(ctypes.byref(p), 256, 256, pop.value, 512, work.value, None,
+                              ctypes.byref(h)) == lbm.LBM_EINVAL  # popA == popB
+    assert lbm.LIB.lbm_create(ctypes.byref(p), 256, 512, 10, 768, work.value, None,
+                              ctypes.byref(h)) == lbm.LBM_ENOMEM
+    assert lbm.LIB.lbm_step_n(None, 1) == lbm.LBM_EINVAL
+    assert lbm.LIB.lbm_stream_copy(None, None, 16, None) == lbm.LBM_EINVAL
+
+
+def test_tile_table(lbm):
+    tiles = lbm.tiles()
+    assert len(tiles) == lbm.LIB.lbm_tile_count()
+    assert all(t["width"] >= 64 and t["rows"] >= 8 for t in tiles)
+    assert len({(t["width"], t["rows"], t["threads"], t["prefetch"]) for t in tiles}) == len(tiles)
+    w = ctypes.c_int32()
+    assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None) == lbm.LBM_EINVAL

@@ -1,0 +1,192 @@
+"""GPU parity of the fused D2Q9 Shan-Chen step against the FP64 oracle.
+
+Every comparison runs the HIP library through its C-ABI (via the ctypes
+binding) and the oracle on the host from the same seeded inputs.  Tolerances:
+one step from an identical FP32-representable state agrees to FP32 rounding
+(1e-6 relative per population); the droplet run of 1000 steps on 64x64 meets
+max |drho|/rho <= 1e-5; tile shapes, repeats and translations are bitwise.
+Method: Li & Zhang, arXiv 2504.10539, Sec. II-A Eq. (1), Sec. III-A.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_10539_amd import inputs
+from tests.gpu_helpers import f32_state, lbm, need_gpu, rel_density_error, set_state_from, to_np, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _sim(nx, ny, G=-5.0, tau=1.0, storage=0, rho0=0.0):
+    return lbm().Simulation(nx, ny, G, tau, storage, rho0)
+
+
+def _rel_pop_err(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("nx,ny,G,tau", [(8, 8, -5.0, 1.0), (8, 8, -5.5, 0.8), (13, 7, -4.5, 0.6),
+                                         (1, 1, -5.0, 1.0), (1, 9, -5.0, 0.9), (9, 1, -5.0, 0.9),
+                                         (2, 2, -5.0, 1.2), (3, 3, 0.0, 1.0), (65, 66, -5.0, 1.0),
+                                         (300, 77, -5.5, 0.7)])
+def test_steps_from_identical_state(nx, ny, G, tau):
+    """A few steps from a random positive FP32-exact state (ragged sizes, degenerate grids)."""
+    f0 = f32_state(inputs.random_positive_state(nx, ny, seed=nx * 131 + ny))
+    for n in (1, 3):
+        ref = oracle.step(f0, G, tau, n)
+        s = _sim(nx, ny, G, tau)
+        set_state_from(s, f0)
+        s.step(n)
+        got = to_np(s.get_state())
+        assert _rel_pop_err(got, ref) < 2e-6 * n, (nx, ny, n)
+
+
+def test_state_roundtrip_is_exact():
+    f0 = f32_state(inputs.random_positive_state(37, 23, seed=1))
+    sim = _sim(37, 23)
+    set_state_from(sim, f0)
+    assert np.array_equal(to_np(sim.get_state()), f0)
+
+
+def test_init_matches_oracle():
+    N = 64
+    drops = inputs.single_droplet(N, 16)
+    sim = _sim(N, N).init_droplets(drops, seed=1)
+    ref = oracle.droplet_state(N, N, drops, seed=1)
+    got = to_np(sim.get_state())
+    # FP64 profile on both sides; the GPU rounds w_i rho to FP32 once
+    assert np.max(np.abs(got - ref) / ref) < 1.2e-7
+
+
+def test_init_window_many_droplets_matches_oracle():
+    """A 256x192 window of a 4096-periodic frame with 2000 droplets and noise."""
+    drops = inputs.many_droplets(4096, 2000, 8, 48, seed=3)
+    sim = _sim(256, 192, G=-5.5, tau=0.8).init_droplets(drops, seed=3, period=(4096, 4096),
+                                                           origin=(1000, 3000))
+    ref = oracle.droplet_state(256, 192, drops, seed=3, period=(4096, 4096), origin=(1000, 3000))
+    got = to_np(sim.get_state())
+    assert np.max(np.abs(got - ref) / ref) < 1.2e-7
+
+
+def test_config1_fp32_1000_steps():
+    """64x64, tau 1, G -5, R 16 droplet, noise 1e-3: max |drho|/rho <= 1e-5 after 1000 steps."""
+    N = 64
+    drops = inputs.single_droplet(N, 16)
+    sim = _sim(N, N, -5.0, 1.0).init_droplets(drops, seed=1)
+    sim.step(1000)
+    rho_gpu = to_np(sim.moments()[0])
+    ref = oracle.step(oracle.droplet_state(N, N, drops, seed=1), -5.0, 1.0, 1000, 8)
+    rho_ref = oracle.density(ref)
+    err = rel_density_error(rho_gpu, rho_ref)
+    print(f"config1 fp32 max|drho|/rho = {err:.3e}")
+    assert err <= 1e-5
+
+
+def test_moments_match_oracle():
+    N = 48
+    f = oracle.step(oracle.droplet_state(N, N, [(20.0, 25.0, 10.0)], seed=2), -5.0, 1.0, 200)
+    f0 = f32_state(f)
+    sim = _sim(N, N)
+    set_state_from(sim, f0)
+    rho, ux, uy = (to_np(t) for t in sim.moments())
+    r_ref, ux_ref, uy_ref = oracle.moments(f0, -5.0)
+    assert np.max(np.abs(rho - r_ref) / r_ref) < 1e-6
+    umax = max(np.abs(ux_ref).max(), np.abs(uy_ref).max())
+    assert np.max(np.abs(ux - ux_ref)) < 1e-5 * umax + 1e-9
+    assert np.max(np.abs(uy - uy_ref)) < 1e-5 * umax + 1e-9
+
+
+def test_metrics_match_oracle_on_identical_field():
+    """FP64 GPU diagnostics vs the oracle's Eqs. (9)-(16) on the same FP32 state."""
+    N = 96
+    f = oracle.step(oracle.droplet_state(N, N, inputs.single_droplet(N, 20), seed=5), -5.0, 1.0,
+                    300)
+    f0 = f32_state(f)
+    sim = _sim(N, N)
+    set_state_from(sim, f0)
+    m = sim.metrics()
+    ref = oracle.metrics(oracle.density(f0))
+    mass, px, py = oracle.conservation(f0)
+    for k in ("W", "Gmax", "drho", "W_eff", "E_int", "rho_max", "rho_min", "sum_grad"):
+        assert abs(m[k] - ref[k]) <= 1e-12 * max(1.0, abs(ref[k])), k
+    assert m["n_above"] == ref["n_above"]
+    assert abs(m["mass"] - mass) <= 1e-12 * mass
+    assert abs(m["mom_x"] - px) <= 1e-12 * mass and abs(m["mom_y"] - py) <= 1e-12 * mass
+    assert m["finite"] == 1
+
+
+def test_metrics_flag_nonfinite_state():
+    f0 = f32_state(inputs.random_positive_state(16, 16, seed=9))
+    f0[3, 4, 5] = np.nan
+    sim = _sim(16, 16)
+    set_state_from(sim, f0)
+    assert sim.metrics()["finite"] == 0
+
+
+def test_mass_and_momentum_drift_fp32():
+    """FP32 storage: mass drift per step is at rounding level (rest population by mass balance)."""
+    N = 128
+    sim = _sim(N, N, -5.0, 1.0).init_droplets(inputs.single_droplet(N, 30), seed=4)
+    m0 = sim.metrics()
+    sim.step(2000)
+    m1 = sim.metrics()
+    assert abs(m1["mass"] / m0["mass"] - 1.0) < 2e-6
+    assert abs(m1["mom_x"]) < 1e-4 * m0["mass"] and abs(m1["mom_y"]) < 1e-4 * m0["mass"]
+
+
+def test_tile_shapes_bitwise_identical():
+    """Every tile shape computes bitwise the same state (ragged grid)."""
+    nx, ny = 300, 77
+    f0 = f32_state(oracle.droplet_state(nx, ny, [(150.0, 38.0, 20.0), (20.0, 70.0, 9.0)], seed=6))
+    ref = None
+    for t in lbm().tiles():
+        sim = _sim(nx, ny, -5.5, 0.8)
+        sim.set_tile(t["id"])
+        set_state_from(sim, f0)
+        sim.step(5)
+        got = to_np(sim.get_state())
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref), t
+
+
+def test_repeat_and_translation_bitwise():
+    nx, ny = 200, 120
+    f0 = f32_state(oracle.droplet_state(nx, ny, [(80.0, 60.0, 25.0)], seed=8))
+    a = _sim(nx, ny)
+    set_state_from(a, f0)
+    a.step(40)
+    b = _sim(nx, ny)
+    set_state_from(b, f0)
+    b.step(40)
+    sa = to_np(a.get_state())
+    assert np.array_equal(sa, to_np(b.get_state()))
+    sx, sy = 37, 11  # not multiples of any strip width or band height
+    c = _sim(nx, ny)
+    set_state_from(c, np.roll(f0, (sy, sx), axis=(1, 2)))
+    c.step(40)
+    assert np.array_equal(np.roll(sa, (sy, sx), axis=(1, 2)), to_np(c.get_state()))
+
+
+def test_autotune_keeps_state_and_result(tmp_path, monkeypatch):
+    monkeypatch.setenv("SCLBM_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    nx, ny = 256, 64
+    f0 = f32_state(oracle.droplet_state(nx, ny, [(100.0, 30.0, 15.0)], seed=2))
+    a = _sim(nx, ny)
+    set_state_from(a, f0)
+    best = a.autotune(reps=2)
+    assert 0 <= best < len(lbm().tiles())
+    assert np.array_equal(to_np(a.get_state()), f0)
+    a.step(10)
+    b = _sim(nx, ny)  # picks the tuned shape from the cache
+    assert b.tile == best
+    b.set_tile(0)
+    set_state_from(b, f0)
+    b.step(10)
+    assert np.array_equal(to_np(a.get_state()), to_np(b.get_state()))
+    assert (tmp_path / "tune.jsonl").read_text().count("\n") == 1
