@@ -40,12 +40,40 @@ struct TileItem {
   int32_t inst, x0, y0, h;
 };
 
+// ------------------------------------------------------------------ layout
+//
+// Populations live in one buffer of 9 * nx * ny elements.  Row-interleaved
+// layout (SCLBM_ROW_LAYOUT = 1, the default): row y of population i starts
+// at element (9 y + i) nx, so the nine rows a step touches around one lattice
+// row are neighbours in memory; plane-major layout (0): plane i of nx * ny
+// elements, row y at (i ny + y) nx.  Either way x is fastest, so a wavefront
+// reads and writes consecutive addresses.  Callers see the plane-major
+// order only (lbm_get_state / lbm_set_state convert).
+#ifndef SCLBM_ROW_LAYOUT
+#define SCLBM_ROW_LAYOUT 1
+#endif
+
+__host__ __device__ __forceinline__ uint64_t row_index(int i, int y, int nx, int ny) {
+#if SCLBM_ROW_LAYOUT
+  (void)ny;
+  return ((uint64_t)y * 9u + (uint64_t)i) * (uint64_t)nx;
+#else
+  return ((uint64_t)i * (uint64_t)ny + (uint64_t)y) * (uint64_t)nx;
+#endif
+}
+
+__host__ __device__ __forceinline__ uint64_t pop_index(int i, int x, int y, int nx, int ny) {
+  return row_index(i, y, nx, ny) + (uint64_t)x;
+}
+
 // ------------------------------------------------------------------ storage
 
-// FP32 populations.
+// FP32 populations.  Stores stream past the caches (the buffer written is
+// read again only by the next step).
 struct StoreF32 {
   using T = float;
   static constexpr int kBytes = 4;
+  static constexpr bool kStream = true;
   template <class P>
   __device__ static __forceinline__ float load(P p, float /*shift*/) { return *p; }
   __device__ static __forceinline__ T pack(float v, float /*shift*/) { return v; }
@@ -55,6 +83,7 @@ struct StoreF32 {
 struct StoreF16S {
   using T = _Float16;
   static constexpr int kBytes = 2;
+  static constexpr bool kStream = false;
   template <class P>
   __device__ static __forceinline__ float load(P p, float shift) {
     return static_cast<float>(*p) + shift;

@@ -2,11 +2,11 @@
 // diagnostics (Li & Zhang, arXiv 2504.10539: Sec. II-A Eq. (1); Sec. III-A
 // initial droplet; Sec. II-D Eqs. (9)-(13) and Sec. IV-F Eqs. (14)-(16)).
 //
-// Population buffers are structure of arrays (plane i of nx*ny, x fastest).
-// A buffer holds post-collision values at the cell they leave from, so the
-// pre-collision state is read by pulling: f_i(x, t) = A_i(x - e_i).  One
-// step reads A and writes the other buffer B at the cell itself; the next
-// step swaps the roles.
+// Population buffers hold the nine populations structure-of-arrays, in the
+// layout of row_index() (sc_device.h).  A buffer holds post-collision values
+// at the cell they leave from, so the pre-collision state is read by pulling:
+// f_i(x, t) = A_i(x - e_i).  One step reads A and writes the other buffer B
+// at the cell itself; the next step swaps the roles.
 
 #include <hip/hip_runtime.h>
 
@@ -32,14 +32,28 @@ struct Strip {
   using T = typename S::T;
   static constexpr int SW = NT * CPT;
 
-  gptr<const T> plane[9];
-  gptr<T> out[9];
+  uint64_t src, dst;  // buffer base addresses (read / written this step)
   float sh[9];
   int nx, ny, x0, y0, h, wcols;
   // Columns of this lane's cells; slot CPT is the halo column (lanes 0, 1).
   int xc[CPT + 1], xm[CPT + 1], xp[CPT + 1];
   bool live[CPT + 1];
   float G, tau, omega;
+
+  // First element of row y of population i.  The address is the same for the
+  // whole workgroup; readfirstlane keeps it in scalar registers, so each load
+  // and store is a scalar base plus the lane's 32-bit column offset.
+  __device__ __forceinline__ static uint64_t uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+  }
+  __device__ __forceinline__ gptr<const T> in_row(int i, int y) const {
+    return as_global<const T>(uniform(src + row_index(i, y, nx, ny) * sizeof(T)));
+  }
+  __device__ __forceinline__ gptr<T> out_row(int i, int y) const {
+    return as_global<T>(uniform(dst + row_index(i, y, nx, ny) * sizeof(T)));
+  }
 
   __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti,
                                         int sub) {
@@ -55,15 +69,11 @@ struct Strip {
     const float rho0 = dp->rho0;
     const int par = (dp->parity + sub) & 1;
     const uint64_t a = dp->pop[0], b = dp->pop[1];
-    const uint64_t src = par ? b : a, dst = par ? a : b;
-    const uint64_t n = (uint64_t)nx * (uint64_t)ny * sizeof(T);
+    src = par ? b : a;
+    dst = par ? a : b;
     const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      plane[i] = as_global<const T>(src + (uint64_t)i * n);
-      out[i] = as_global<T>(dst + (uint64_t)i * n);
-      sh[i] = ws[i] * rho0;
-    }
+    for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
     const int t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -85,26 +95,37 @@ struct Strip {
     }
   }
 
-  // Pre-collision populations of row (y0 + j) mod ny for every live slot.
+  // Element at byte offset `boff` (32-bit, lane-varying) from a uniform row base.
+  __device__ __forceinline__ static gptr<const T> at(gptr<const T> base, uint32_t boff) {
+    return reinterpret_cast<gptr<const T>>(reinterpret_cast<gptr<const char>>(base) + boff);
+  }
+  __device__ __forceinline__ static gptr<T> at(gptr<T> base, uint32_t boff) {
+    return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) + boff);
+  }
+
+  // Pre-collision populations of row (y0 + j) mod ny for every live slot:
+  // f_i(x, y) = A_i(x - e_i), so population i is read from row y - e_iy.
   __device__ __forceinline__ void pull(int j, float (&f)[CPT + 1][9]) const {
     int y = y0 + j;
     y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-    const uint32_t r0 = (uint32_t)y * (uint32_t)nx;
-    const uint32_t rm = (uint32_t)wrap_dec(y, ny) * (uint32_t)nx;
-    const uint32_t rp = (uint32_t)wrap_inc(y, ny) * (uint32_t)nx;
+    const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+    const gptr<const T> p0 = in_row(0, y), p1 = in_row(1, y), p2 = in_row(2, ym),
+                        p3 = in_row(3, y), p4 = in_row(4, yp), p5 = in_row(5, ym),
+                        p6 = in_row(6, ym), p7 = in_row(7, yp), p8 = in_row(8, yp);
+    constexpr uint32_t B = sizeof(T);
 #pragma unroll
     for (int k = 0; k <= CPT; ++k) {
       if (live[k]) {
-        const uint32_t c = xc[k], m = xm[k], p = xp[k];
-        f[k][0] = S::load(plane[0] + (r0 + c), sh[0]);
-        f[k][1] = S::load(plane[1] + (r0 + m), sh[1]);
-        f[k][2] = S::load(plane[2] + (rm + c), sh[2]);
-        f[k][3] = S::load(plane[3] + (r0 + p), sh[3]);
-        f[k][4] = S::load(plane[4] + (rp + c), sh[4]);
-        f[k][5] = S::load(plane[5] + (rm + m), sh[5]);
-        f[k][6] = S::load(plane[6] + (rm + p), sh[6]);
-        f[k][7] = S::load(plane[7] + (rp + p), sh[7]);
-        f[k][8] = S::load(plane[8] + (rp + m), sh[8]);
+        const uint32_t c = (uint32_t)xc[k] * B, m = (uint32_t)xm[k] * B, p = (uint32_t)xp[k] * B;
+        f[k][0] = S::load(at(p0, c), sh[0]);
+        f[k][1] = S::load(at(p1, m), sh[1]);
+        f[k][2] = S::load(at(p2, c), sh[2]);
+        f[k][3] = S::load(at(p3, p), sh[3]);
+        f[k][4] = S::load(at(p4, c), sh[4]);
+        f[k][5] = S::load(at(p5, m), sh[5]);
+        f[k][6] = S::load(at(p6, p), sh[6]);
+        f[k][7] = S::load(at(p7, p), sh[7]);
+        f[k][8] = S::load(at(p8, m), sh[8]);
       }
     }
   }
@@ -126,7 +147,9 @@ struct Strip {
     const float* dn = ring[r & 3];
     const float* md = ring[(r + 1) & 3];
     const float* up = ring[(r + 2) & 3];
-    const uint32_t row = (uint32_t)(y0 + r) * (uint32_t)nx;
+    gptr<T> o[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = out_row(i, y0 + r);
     const int t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -137,9 +160,14 @@ struct Strip {
                dn[c + 1], G, Fx, Fy);
       const float rho = density(f[k]);
       collide(f[k], rho, Fx, Fy, tau, omega);
-      const uint32_t o = row + (uint32_t)xc[k];
+      const uint32_t xb = (uint32_t)xc[k] * (uint32_t)sizeof(T);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) out[i][o] = S::pack(f[k][i], sh[i]);
+      for (int i = 0; i < 9; ++i) {
+        if constexpr (S::kStream)
+          __builtin_nontemporal_store(S::pack(f[k][i], sh[i]), at(o[i], xb));
+        else
+          *at(o[i], xb) = S::pack(f[k][i], sh[i]);
+      }
     }
   }
 };
@@ -246,19 +274,19 @@ __global__ void k_tick_end(InstDesc* descs, int n) {
 template <class S>
 __device__ __forceinline__ void pull_cell(const typename S::T* src, size_t n, int nx, int ny, int x,
                                           int y, float rho0, float f[9]) {
+  (void)n;
   const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
   const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-  const size_t r0 = (size_t)y * nx, rm = (size_t)ym * nx, rp = (size_t)yp * nx;
   const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-  f[0] = S::load(src + 0 * n + r0 + x, ws[0] * rho0);
-  f[1] = S::load(src + 1 * n + r0 + xm, ws[1] * rho0);
-  f[2] = S::load(src + 2 * n + rm + x, ws[2] * rho0);
-  f[3] = S::load(src + 3 * n + r0 + xp, ws[3] * rho0);
-  f[4] = S::load(src + 4 * n + rp + x, ws[4] * rho0);
-  f[5] = S::load(src + 5 * n + rm + xm, ws[5] * rho0);
-  f[6] = S::load(src + 6 * n + rm + xp, ws[6] * rho0);
-  f[7] = S::load(src + 7 * n + rp + xp, ws[7] * rho0);
-  f[8] = S::load(src + 8 * n + rp + xm, ws[8] * rho0);
+  f[0] = S::load(src + pop_index(0, x, y, nx, ny), ws[0] * rho0);
+  f[1] = S::load(src + pop_index(1, xm, y, nx, ny), ws[1] * rho0);
+  f[2] = S::load(src + pop_index(2, x, ym, nx, ny), ws[2] * rho0);
+  f[3] = S::load(src + pop_index(3, xp, y, nx, ny), ws[3] * rho0);
+  f[4] = S::load(src + pop_index(4, x, yp, nx, ny), ws[4] * rho0);
+  f[5] = S::load(src + pop_index(5, xm, ym, nx, ny), ws[5] * rho0);
+  f[6] = S::load(src + pop_index(6, xp, ym, nx, ny), ws[6] * rho0);
+  f[7] = S::load(src + pop_index(7, xp, yp, nx, ny), ws[7] * rho0);
+  f[8] = S::load(src + pop_index(8, xm, yp, nx, ny), ws[8] * rho0);
 }
 
 // Moments, pass 1: rho (FP32, the step kernel's summation order).
@@ -331,7 +359,7 @@ __global__ __launch_bounds__(256) void k_set_state(const float* __restrict__ f_i
       int xs = x + ex[i], ys = y + ey[i];
       xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      dst[i * n + c] = S::pack(f_in[i * n + (size_t)ys * nx + xs], ws[i] * rho0);
+      dst[pop_index(i, x, y, nx, ny)] = S::pack(f_in[i * n + (size_t)ys * nx + xs], ws[i] * rho0);
     }
   }
 }
@@ -434,7 +462,7 @@ __global__ __launch_bounds__(256) void k_init_pop(const double* __restrict__ rho
       xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
       const float f = (float)(wd[i] * rho[(size_t)ys * nx + xs]);
-      dst[i * n + c] = S::pack(f, ws[i] * rho0);
+      dst[pop_index(i, x, y, nx, ny)] = S::pack(f, ws[i] * rho0);
     }
   }
 }
@@ -607,30 +635,24 @@ using StepLauncher = hipError_t (*)(const InstDesc*, const TileItem*, const int*
                                     hipStream_t);
 using StepFn = const void* (*)();
 
-#define SCLBM_VARIANT(NT, CPT, PF) {NT, CPT, PF}
-constexpr StepVariant kVariants[] = {
-    SCLBM_VARIANT(64, 1, 1),  SCLBM_VARIANT(64, 1, 2),  SCLBM_VARIANT(128, 1, 1),
-    SCLBM_VARIANT(128, 1, 2), SCLBM_VARIANT(64, 4, 1),  SCLBM_VARIANT(128, 2, 1),
-    SCLBM_VARIANT(128, 2, 2), SCLBM_VARIANT(256, 1, 1), SCLBM_VARIANT(256, 1, 2),
-    SCLBM_VARIANT(256, 2, 1), SCLBM_VARIANT(512, 1, 1),
-};
-#undef SCLBM_VARIANT
+// Step-kernel variants (threads, cells per thread, rows in flight); the order
+// fixes the tile-shape numbering.
+#define SCLBM_STEP_VARIANTS(X)                                                          \
+  X(64, 1, 1) X(64, 1, 2) X(128, 1, 1) X(128, 1, 2) X(64, 4, 1) X(128, 2, 1) X(128, 2, 2) \
+  X(256, 1, 1) X(256, 1, 2) X(256, 2, 1) X(512, 1, 1) X(512, 1, 2) X(256, 2, 2)         \
+  X(1024, 1, 1)
 
+#define SCLBM_AS_VARIANT(NT, CPT, PF) StepVariant{NT, CPT, PF},
+#define SCLBM_AS_LAUNCH(NT, CPT, PF) launch_step_t<S, NT, CPT, PF>,
+#define SCLBM_AS_FN(NT, CPT, PF) step_fn_t<S, NT, CPT, PF>,
+constexpr StepVariant kVariants[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_VARIANT)};
 template <class S>
-constexpr StepLauncher kLaunch[] = {
-    launch_step_t<S, 64, 1, 1>,  launch_step_t<S, 64, 1, 2>,  launch_step_t<S, 128, 1, 1>,
-    launch_step_t<S, 128, 1, 2>, launch_step_t<S, 64, 4, 1>,  launch_step_t<S, 128, 2, 1>,
-    launch_step_t<S, 128, 2, 2>, launch_step_t<S, 256, 1, 1>, launch_step_t<S, 256, 1, 2>,
-    launch_step_t<S, 256, 2, 1>, launch_step_t<S, 512, 1, 1>,
-};
-
+constexpr StepLauncher kLaunch[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_LAUNCH)};
 template <class S>
-constexpr StepFn kFn[] = {
-    step_fn_t<S, 64, 1, 1>,  step_fn_t<S, 64, 1, 2>,  step_fn_t<S, 128, 1, 1>,
-    step_fn_t<S, 128, 1, 2>, step_fn_t<S, 64, 4, 1>,  step_fn_t<S, 128, 2, 1>,
-    step_fn_t<S, 128, 2, 2>, step_fn_t<S, 256, 1, 1>, step_fn_t<S, 256, 1, 2>,
-    step_fn_t<S, 256, 2, 1>, step_fn_t<S, 512, 1, 1>,
-};
+constexpr StepFn kFn[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_FN)};
+#undef SCLBM_AS_VARIANT
+#undef SCLBM_AS_LAUNCH
+#undef SCLBM_AS_FN
 
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 

@@ -14,7 +14,7 @@ namespace sclbm {
 struct StepVariant {
   int threads, cells, prefetch;
 };
-constexpr int kNumVariants = 11;
+constexpr int kNumVariants = 14;
 // Band heights a tile shape may use; tile shape k = variant * kNumRows + row index.
 constexpr int kRowChoices[] = {8, 16, 32, 64, 128};
 constexpr int kNumRows = 5;

@@ -98,8 +98,9 @@ int default_tile(const lbm_params& p) {
   // variant index * kNumRows + row index; see kVariants / kRowChoices.
   if (p.nx <= 64) return 0 * kNumRows + 0;   // 64 threads, 1 cell, 8 rows
   if (p.nx <= 128) return 2 * kNumRows + 1;  // 128 threads, 16 rows
-  if (p.nx <= 512) return 7 * kNumRows + 2;  // 256 threads, 32 rows
-  return 10 * kNumRows + 3;                  // 512 threads, 64 rows
+  if (p.storage == LBM_F16_SHIFTED)
+    return 9 * kNumRows + 2;                 // 256 threads x 2 cells, 32 rows
+  return 8 * kNumRows + 0;                   // 256 threads, 2 rows in flight, 8 rows
 }
 
 std::string device_arch() {

@@ -16,7 +16,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libsclbm.so")
+# SCLBM_LIB may name another build of the same library (e.g. a variant build).
+LIB_PATH = os.environ.get("SCLBM_LIB") or os.path.join(_HERE, "_lib", "libsclbm.so")
 
 LBM_OK = 0
 LBM_EINVAL = -1

@@ -1,0 +1,114 @@
+"""Serving loop on the GPU: each result is the same alone and in the mix.
+
+Requests of uneven sizes and both storage types are admitted while others run
+(continuous batching); every final state must equal, bitwise, the same
+request run alone on a server and run by the plain single-run path.  A
+request with unstable parameters is flagged without disturbing the others.
+"""
+import numpy as np
+import pytest
+
+from paper_2504_10539_amd import inputs
+from tests.gpu_helpers import lbm, need_gpu, to_np, torch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+REQS = [  # nx, G, tau, steps, drops, storage
+    (64, -5.0, 1.0, 300, [(32, 32, 12)], 0),
+    (150, -5.5, 0.9, 170, [(70, 75, 25), (120, 40, 10)], 0),
+    (256, -4.8, 1.1, 95, [(128, 128, 40)], 1),
+    (97, -5.2, 0.8, 240, [(50, 50, 20)], 0),
+    (200, -5.0, 1.0, 33, [(100, 100, 30)], 1),
+    (128, -6.0, 0.7, 130, [(64, 64, 20)], 0),
+]
+
+
+def _submit(srv, k, r):
+    n, G, tau, steps, drops, storage = r
+    f_out = torch.empty((9, n, n), dtype=torch.float32, device="cuda")
+    t = srv.submit(n, n, G, tau, steps, drops, storage=storage, rho0=0.5 if storage else 0.0,
+                   seed=k + 1, f_out=f_out)
+    return t, f_out
+
+
+def _solo_plain(k, r):
+    n, G, tau, steps, drops, storage = r
+    s = lbm().Simulation(n, n, G, tau, storage, 0.5 if storage else 0.0)
+    s.init_droplets(drops, seed=k + 1)
+    s.step(steps)
+    return s.get_state().cpu().numpy()
+
+
+def _bits(a):
+    """Bit patterns, so that non-finite results compare too."""
+    return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
+
+
+def test_results_equal_alone_and_in_the_mix():
+    L = lbm()
+    srv = L.Server(2 << 30, steps_per_tick=16, max_slots=8)
+    outs = [_submit(srv, k, r) for k, r in enumerate(REQS)]
+    srv.drain()
+    mixed, codes = [], []
+    for t, f in outs:
+        code, m = srv.poll(t)
+        assert code in (L.LBM_OK, L.LBM_EUNSTABLE)
+        assert m["t_submit"] <= m["t_admit"] <= m["t_done"]
+        mixed.append(f.cpu().numpy())
+        codes.append(code)
+    assert codes.count(L.LBM_OK) >= 4
+    assert srv.stats()["completed"] == len(REQS)
+    srv.close()
+    for k, r in enumerate(REQS):
+        alone = L.Server(1 << 30, steps_per_tick=16, max_slots=8)
+        t, f = _submit(alone, k, r)
+        alone.drain()
+        assert alone.poll(t)[0] == codes[k]
+        assert np.array_equal(_bits(f.cpu().numpy()), _bits(mixed[k])), k
+        alone.close()
+        assert np.array_equal(_bits(_solo_plain(k, r)), _bits(mixed[k])), k
+
+
+def test_fifo_policy_matches_continuous():
+    L = lbm()
+    srv = L.Server(1 << 30, policy=L.LBM_POLICY_FIFO, steps_per_tick=16)
+    outs = [_submit(srv, k, r) for k, r in enumerate(REQS[:3])]
+    srv.drain()
+    for k, (t, f) in enumerate(outs):
+        assert srv.poll(t)[0] == L.LBM_OK
+        assert np.array_equal(to_np(f), _solo_plain(k, REQS[k]))
+    srv.close()
+
+
+def test_unstable_request_is_flagged_and_isolated():
+    L = lbm()
+    srv = L.Server(1 << 30, steps_per_tick=16)
+    good = _submit(srv, 0, REQS[0])
+    bad_req = (64, -7.5, 0.52, 400, [(32, 32, 14)], 0)
+    bad = _submit(srv, 9, bad_req)
+    srv.drain()
+    assert srv.poll(bad[0])[0] == L.LBM_EUNSTABLE
+    assert srv.poll(good[0])[0] == L.LBM_OK
+    assert np.array_equal(to_np(good[1]), _solo_plain(0, REQS[0]))
+    srv.close()
+
+
+def test_poisson_trace_completes_within_budget():
+    L = lbm()
+    trace = inputs.serving_trace(24, rate=200.0, seed=4, nmax=512, smax=600)
+    pool = 256 << 20
+    srv = L.Server(pool, steps_per_tick=16, max_slots=64)
+    ts = [srv.submit(r.n, r.n, r.G, r.tau, r.steps, r.drops, seed=r.seed) for r in trace]
+    srv.drain()
+    codes = [srv.poll(t)[0] for t in ts]
+    st = srv.stats()
+    assert st["completed"] == len(trace)
+    assert st["pool_high_water"] <= pool
+    assert all(c in (L.LBM_OK, L.LBM_EUNSTABLE) for c in codes)
+    srv.close()
