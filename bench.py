@@ -70,7 +70,7 @@ def run_main(args, torch, lbm, inputs):
     for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted")):
         if storage == lbm.LBM_F16_SHIFTED and args.no_fp16:
             continue
-        rho0 = 0.5 if storage == lbm.LBM_F16_SHIFTED else 0.0
+        rho0 = 1.0 if storage == lbm.LBM_F16_SHIFTED else 0.0
         sim = lbm.Simulation(N, N, args.G, args.tau, storage, rho0)
         sim.init_droplets(drops, seed=3)
         if args.tile >= 0:
@@ -152,10 +152,11 @@ def run_sweep(args, torch, lbm, inputs):
     for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted")):
         sims = []
         for k, (G, tau) in enumerate(pairs):
-            s = lbm.Simulation(256, 256, G, tau, storage, 0.5 if storage else 0.0)
+            s = lbm.Simulation(256, 256, G, tau, storage, 1.0 if storage else 0.0)
             s.init_droplets(inputs.single_droplet(256, 40), seed=k)
             sims.append(s)
         batch = lbm.Batch(sims, steps_per_graph=args.graph_steps)
+        tile = batch.autotune(reps=2) if not args.no_autotune else -1
         batch.step(args.graph_steps)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -172,7 +173,7 @@ def run_sweep(args, torch, lbm, inputs):
         bpu = BYTES_F32 if storage == lbm.LBM_F32 else BYTES_F16
         res[name] = {"mlups": lu / wall / 1e6, "gpu_mlups": lu / (ms * 1e-3) / 1e6,
                      "achieved_gbs": lu * bpu / (ms * 1e-3) / 1e9, "instances": len(sims),
-                     "steps": args.sweep_steps, "unstable_instances": unstable}
+                     "steps": args.sweep_steps, "unstable_instances": unstable, "tile": tile}
         log(f"[sweep {name}] {res[name]['gpu_mlups']:.0f} MLUPS, {unstable} unstable")
         for s in sims:
             s.close()

@@ -16,8 +16,11 @@
  * Conventions shared by every entry point:
  *   - Velocities e0 = (0,0); e1..e4 = (1,0) (0,1) (-1,0) (0,-1);
  *     e5..e8 = (1,1) (-1,1) (-1,-1) (1,-1); weights 4/9, 1/9, 1/36.
- *   - Population and field arrays are structure-of-arrays, plane i of
- *     nx * ny elements, x fastest: element (i, y, x) at i*nx*ny + y*nx + x.
+ *   - Arrays a caller reads or writes are plane-major, x fastest: population
+ *     states (lbm_get_state / lbm_set_state) have element (i, y, x) at
+ *     i*nx*ny + y*nx + x, fields (lbm_moments) element (y, x) at y*nx + x.
+ *     The layout inside the two population buffers is private to the
+ *     library (row-interleaved: row y of population i at (9 y + i) nx).
  *   - "State at step t" means the pre-collision populations f_i(x, t).
  *   - Device pointers are HIP device addresses (e.g. torch tensors on the
  *     GPU).  The library never allocates, frees or retains device memory
@@ -132,7 +135,7 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
  * call; n = 0 gives a uniform rho_g plus noise.  Uses the second population
  * buffer as scratch (8 bytes per cell for rho, then the droplet list), so n
  * is limited to (pop_bytes - 8 nx ny) / 24; LBM_EINVAL beyond that or for
- * bad lbm_init fields.  Asynchronous. */
+ * bad lbm_init fields.  Synchronises the stream. */
 lbm_status lbm_init_droplets(lbm_ctx* ctx, const double* drops, int32_t n, const lbm_init* ip);
 
 /* Enqueues n >= 0 time steps (Eq. (1)): one fused pull-stream, force and
@@ -202,6 +205,13 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* work, size_t 
 
 /* Enqueues n time steps of every member.  Asynchronous. */
 lbm_status lbm_batch_step_n(lbm_batch* b, int64_t n);
+
+/* Times every tile shape on the whole batch (each shape `reps` launches in
+ * which every member reads its current buffer and writes its idle one, so no
+ * state changes) and rebuilds the batch's graph with the fastest shape for
+ * all members; members' own single-run tile shapes are left as they are.
+ * Synchronises.  *best (may be NULL) receives the chosen shape. */
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best);
 
 /* Releases the batch (synchronises the stream); members become free again. */
 lbm_status lbm_batch_destroy(lbm_batch* b);

@@ -35,10 +35,13 @@ struct InstDesc {
 static_assert(sizeof(InstDesc) == 80, "InstDesc layout");
 
 // One unit of step-kernel work: rows [y0, y0 + h) of the strip of columns
-// starting at x0 of simulation `inst`.
+// starting at x0 of simulation `inst`, marched downwards (dir = 0, from y0)
+// or upwards (dir = 1, from y0 + h - 1).
 struct TileItem {
-  int32_t inst, x0, y0, h;
+  int32_t inst, x0, y0;
+  int16_t h, dir;
 };
+static_assert(sizeof(TileItem) == 16, "TileItem layout");
 
 // ------------------------------------------------------------------ layout
 //

@@ -34,7 +34,7 @@ struct Strip {
 
   uint64_t src, dst;  // buffer base addresses (read / written this step)
   float sh[9];
-  int nx, ny, x0, y0, h, wcols;
+  int nx, ny, x0, y0, h, dir, wcols;
   // Columns of this lane's cells; slot CPT is the halo column (lanes 0, 1).
   int xc[CPT + 1], xm[CPT + 1], xp[CPT + 1];
   bool live[CPT + 1];
@@ -62,6 +62,7 @@ struct Strip {
     x0 = ti.x0;
     y0 = ti.y0;
     h = ti.h;
+    dir = ti.dir;
     wcols = min(SW, nx - x0);
     G = dp->G;
     tau = dp->tau;
@@ -103,11 +104,16 @@ struct Strip {
     return reinterpret_cast<gptr<T>>(reinterpret_cast<gptr<char>>(base) + boff);
   }
 
-  // Pre-collision populations of row (y0 + j) mod ny for every live slot:
-  // f_i(x, y) = A_i(x - e_i), so population i is read from row y - e_iy.
+  // Lattice row of march position j (j = -1 and j = h are the halo rows).
+  __device__ __forceinline__ int row_of(int j) const {
+    int y = dir ? y0 + h - 1 - j : y0 + j;
+    return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+  }
+
+  // Pre-collision populations of the row at march position j for every live
+  // slot: f_i(x, y) = A_i(x - e_i), so population i is read from row y - e_iy.
   __device__ __forceinline__ void pull(int j, float (&f)[CPT + 1][9]) const {
-    int y = y0 + j;
-    y = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    const int y = row_of(j);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
     const gptr<const T> p0 = in_row(0, y), p1 = in_row(1, y), p2 = in_row(2, ym),
                         p3 = in_row(3, y), p4 = in_row(4, yp), p5 = in_row(5, ym),
@@ -130,7 +136,8 @@ struct Strip {
     }
   }
 
-  // psi of row j into ring slot (j + 1) & 3 (LDS column index = strip column + 1).
+  // psi of march position j into ring slot (j + 1) & 3 (LDS column index =
+  // strip column + 1).
   __device__ __forceinline__ void publish(int j, const float (&f)[CPT + 1][9],
                                           float (*ring)[SW + 2]) const {
     float* row = ring[(j + 1) & 3];
@@ -141,15 +148,20 @@ struct Strip {
     if (live[CPT]) row[t == 0 ? 0 : wcols + 1] = psi_of(density(f[CPT]));
   }
 
-  // Collide row r (psi of rows r-1, r, r+1 already in the ring) and store it.
+  // Collide the row at march position r (psi of positions r-1, r, r+1 already
+  // in the ring) and store it.  Marching upwards, the previous position is
+  // the row above (y + 1) and the next one the row below.
   __device__ __forceinline__ void finish(int r, float (&f)[CPT + 1][9],
                                          const float (*ring)[SW + 2]) const {
-    const float* dn = ring[r & 3];
+    const float* prev = ring[r & 3];
     const float* md = ring[(r + 1) & 3];
-    const float* up = ring[(r + 2) & 3];
+    const float* next = ring[(r + 2) & 3];
+    const float* dn = dir ? next : prev;
+    const float* up = dir ? prev : next;
     gptr<T> o[9];
+    const int y = row_of(r);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) o[i] = out_row(i, y0 + r);
+    for (int i = 0; i < 9; ++i) o[i] = out_row(i, y);
     const int t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < CPT; ++k) {
@@ -172,17 +184,29 @@ struct Strip {
   }
 };
 
+// Work distribution: with grab == nullptr workgroup b takes items b, b + grid,
+// ...; otherwise each workgroup takes the next item from the counter *grab
+// (zeroed before the launch) until the table is exhausted, which balances
+// persistent grids over items of unequal cost.
 template <class S, int NT, int CPT, int PF>
 __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
                                              const TileItem* __restrict__ items,
-                                             const int* __restrict__ nitems_p, int sub) {
+                                             const int* __restrict__ nitems_p, int sub,
+                                             int* __restrict__ grab) {
   using St = Strip<S, NT, CPT>;
   __shared__ float ring[4][St::SW + 2];
+  __shared__ int next_item;
   const int nitems = *nitems_p;
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  int it = blockIdx.x;
+  if (grab) {
+    if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
+    __syncthreads();
+    it = next_item;
+  }
+  for (; it < nitems;) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
-    if (sub >= dp->nsub) continue;
+    if (sub < dp->nsub) {
     St s;
     s.setup(dp, ti, sub);
     const int h = s.h;
@@ -232,15 +256,25 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
         if (++r >= h) break;
       }
     }
-    __syncthreads();  // the next item reuses the ring
+    }
+    __syncthreads();  // the next item reuses the ring (and next_item)
+    if (grab) {
+      if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
+      __syncthreads();
+      it = next_item;
+    } else {
+      it += gridDim.x;
+    }
   }
 }
 
 // ============================================================== batched ticks
 
-// Start of a graph replay: every simulation takes min(K, remaining) steps.
-__global__ void k_tick_begin(InstDesc* descs, int n, int K) {
+// Start of a graph replay: every simulation takes min(K, remaining) steps,
+// and the work counters of the replay's step launches start at zero.
+__global__ void k_tick_begin(InstDesc* descs, int n, int K, int* counters, int ncounters) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncounters) counters[i] = 0;
   if (i < n) {
     const int64_t rem = descs[i].remaining;
     descs[i].nsub = (int32_t)(rem < K ? (rem > 0 ? rem : 0) : K);
@@ -622,7 +656,7 @@ template <class S, int NT, int CPT, int PF>
 hipError_t launch_step_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                          int grid, int sub, hipStream_t st) {
   hipLaunchKernelGGL((k_step<S, NT, CPT, PF>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
-                     sub);
+                     sub, (int*)nullptr);
   return hipGetLastError();
 }
 
@@ -679,11 +713,6 @@ hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu) {
                                                       kVariants[variant].threads, 0);
 }
 
-hipError_t launch_tick_begin(InstDesc* descs, int n, int K, hipStream_t st) {
-  hipLaunchKernelGGL(k_tick_begin, dim3((n + 255) / 256), dim3(256), 0, st, descs, n, K);
-  return hipGetLastError();
-}
-
 hipError_t launch_tick_end(InstDesc* descs, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_tick_end, dim3((n + 255) / 256), dim3(256), 0, st, descs, n);
   return hipGetLastError();
@@ -696,8 +725,8 @@ hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t s
 
 hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t nd,
                           int storage, int variant, const InstDesc* descs, const TileItem* items,
-                          const int* nitems, int grid, int sub) {
-  void* args[] = {(void*)&descs, (void*)&items, (void*)&nitems, (void*)&sub};
+                          const int* nitems, int grid, int sub, int* grab) {
+  void* args[] = {(void*)&descs, (void*)&items, (void*)&nitems, (void*)&sub, (void*)&grab};
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(storage == 0 ? kFn<StoreF32>[variant]() : kFn<StoreF16S>[variant]());
   kp.gridDim = dim3(grid);
@@ -709,12 +738,13 @@ hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
 }
 
 hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps,
-                          size_t nd, bool begin, InstDesc* descs, int n, int K) {
+                          size_t nd, bool begin, InstDesc* descs, int n, int K, int* counters,
+                          int ncounters) {
   hipKernelNodeParams kp{};
-  void* args_b[] = {(void*)&descs, (void*)&n, (void*)&K};
+  void* args_b[] = {(void*)&descs, (void*)&n, (void*)&K, (void*)&counters, (void*)&ncounters};
   void* args_e[] = {(void*)&descs, (void*)&n};
   kp.func = begin ? reinterpret_cast<void*>(&k_tick_begin) : reinterpret_cast<void*>(&k_tick_end);
-  kp.gridDim = dim3((n + 255) / 256);
+  kp.gridDim = dim3((std::max(n, ncounters) + 255) / 256);
   kp.blockDim = dim3(256);
   kp.sharedMemBytes = 0;
   kp.kernelParams = begin ? args_b : args_e;

@@ -22,6 +22,9 @@ constexpr int kNumTiles = kNumVariants * kNumRows;
 constexpr int kMinStripWidth = 64;
 constexpr int kMinRows = 8;
 
+// Longest graph of batched steps (time steps per replay).
+constexpr int kMaxGraphSteps = 4096;
+
 // Reductions: at most kMaxPartials blocks, kPartialStride doubles each.
 constexpr int kMaxPartials = 2048;
 constexpr int kPartialStride = 16;
@@ -35,10 +38,10 @@ struct InitArgs {
 
 const StepVariant& step_variant(int v);
 
+// One step launch; grab == nullptr (static assignment of items to workgroups).
 hipError_t launch_step(int storage, int variant, const InstDesc* descs, const TileItem* items,
                        const int* nitems, int grid, int sub, hipStream_t st);
 hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu);
-hipError_t launch_tick_begin(InstDesc* descs, int n, int K, hipStream_t st);
 hipError_t launch_tick_end(InstDesc* descs, int n, hipStream_t st);
 hipError_t launch_moments(int storage, const void* src, int nx, int ny, float rho0, float G,
                           float* rho, float* ux, float* uy, hipStream_t st);

@@ -73,10 +73,15 @@ WorkLayout work_layout(int nx, int ny) {
   return w;
 }
 
+// Bands alternate their march direction, so the two bands on either side of
+// a band boundary reach the rows they share at the same time (both at the
+// start or both at the end of their march) and read them once from L2.
 void make_items(int nx, int ny, int tile, int inst, std::vector<TileItem>& out) {
   const int sw = tile_width(tile), rows = tile_rows(tile);
-  for (int y0 = 0; y0 < ny; y0 += rows)
-    for (int x0 = 0; x0 < nx; x0 += sw) out.push_back({inst, x0, y0, std::min(rows, ny - y0)});
+  int band = 0;
+  for (int y0 = 0; y0 < ny; y0 += rows, ++band)
+    for (int x0 = 0; x0 < nx; x0 += sw)
+      out.push_back({inst, x0, y0, (int16_t)std::min(rows, ny - y0), (int16_t)(band & 1)});
 }
 
 std::vector<TileItem> xcd_order(const std::vector<TileItem>& items) {
@@ -267,13 +272,15 @@ lbm_status lbm_ctx::diagnostics(lbm_metrics* out) {
 namespace sclbm {
 hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t nd,
                           int storage, int variant, const InstDesc* descs, const TileItem* items,
-                          const int* nitems, int grid, int sub);
+                          const int* nitems, int grid, int sub, int* grab);
 hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps,
-                          size_t nd, bool begin, InstDesc* descs, int n, int K);
+                          size_t nd, bool begin, InstDesc* descs, int n, int K, int* counters,
+                          int ncounters);
 hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t st);
 
-size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[2]) {
+size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[2], int K) {
   size_t o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
+  o += align_up((size_t)2 * K * sizeof(int), 256);  // work counters
   for (int s = 0; s < 2; ++s) o += 256 + align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
   return o;
 }
@@ -284,11 +291,13 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   stream = st;
   K = steps_per_tick;
   cap_inst = cap_inst_;
-  if (wbytes < work_bytes(cap_inst, cap_items_)) return fail(LBM_ENOMEM, "batch workspace too small");
+  if (wbytes < work_bytes(cap_inst, cap_items_, K)) return fail(LBM_ENOMEM, "batch workspace too small");
   char* w = reinterpret_cast<char*>(work);
   size_t o = 0;
   d_desc = reinterpret_cast<InstDesc*>(w);
   o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
+  d_counters = reinterpret_cast<int*>(w + o);
+  o += align_up((size_t)2 * K * sizeof(int), 256);
   const int cus = device_cu_count();
   for (int s = 0; s < 2; ++s) {
     cap_items[s] = cap_items_[s];
@@ -301,8 +310,11 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
     if (variant[s] < 0 || cap_items[s] == 0) continue;
     int occ = 0;
     SCLBM_HIP(step_occupancy(s, variant[s], &occ));
+    // Persistent engines (item counts change between replays) run a grid
+    // sized to the resident capacity; fixed ones launch one workgroup per
+    // item, so the hardware overlaps one item's tail with the next item's loads.
     const int cap = std::max(8, std::max(occ, 1) * cus / 8 * 8);
-    grid[s] = std::min(cap_items[s], cap);
+    grid[s] = persistent ? std::min(cap_items[s], cap) : cap_items[s];
   }
   SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc), (size_t)cap_inst * sizeof(InstDesc),
                           hipHostMallocDefault));
@@ -315,22 +327,23 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   // Graph: tick_begin -> K x (one persistent step launch per storage type) -> tick_end.
   SCLBM_HIP(hipGraphCreate(&graph, 0));
   hipGraphNode_t prev;
-  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K));
+  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K, d_counters, 2 * K));
   for (int j = 0; j < K; ++j)
     for (int s = 0; s < 2; ++s) {
       if (grid[s] == 0) continue;
       hipGraphNode_t node;
       SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, variant[s], d_desc, d_items[s],
-                               d_nitems[s], grid[s], j));
+                               d_nitems[s], grid[s], j, dynamic ? d_counters + 2 * j + s : nullptr));
       prev = node;
     }
   hipGraphNode_t last;
-  SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K));
+  SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K, nullptr, 0));
   SCLBM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   return LBM_OK;
 }
 
-lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining) {
+lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining,
+                             int nsub_init) {
   if ((int)m.size() > cap_inst) return fail(LBM_EINVAL, "too many batch members");
   // The staging buffers may still feed the previous upload.
   if (staged_pending) SCLBM_HIP(hipEventSynchronize(staged));
@@ -342,13 +355,13 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
       lbm_ctx* c = m[i];
       d = c->host_desc();
       d.parity = c->parity;
-      d.nsub = 0;
+      d.nsub = nsub_init;
       d.remaining = remaining[i];
       d.steps = c->steps;
       const int s = c->p.storage;
       if (grid[s] == 0) return fail(LBM_EINVAL, "batch has no kernel for this storage type");
       std::vector<TileItem> items;
-      make_items(c->p.nx, c->p.ny, variant[s] * kNumRows + (c->tile % kNumRows), i, items);
+      make_items(c->p.nx, c->p.ny, member_tile(c, variant[s], tile_override), i, items);
       if (count[s] + (int)items.size() > cap_items[s])
         return fail(LBM_ENOMEM, "batch tile table full");
       std::copy(items.begin(), items.end(), h_items[s] + count[s]);
@@ -401,6 +414,12 @@ void BatchEngine::destroy() {
   h_items[0] = h_items[1] = nullptr;
 }
 
+// Tile a member uses inside a batch: the batch's override if set, else the
+// batch's strip variant with the member's own band height.
+int member_tile(const lbm_ctx* c, int variant, int tile_override) {
+  return tile_override >= 0 ? tile_override : variant * kNumRows + (c->tile % kNumRows);
+}
+
 // Strip variant used for one storage type: that of the widest member's tile.
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   int best = -1, bestn = -1;
@@ -412,12 +431,12 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   return best;
 }
 
-int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant) {
+int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override) {
   int n = 0;
   for (lbm_ctx* c : m) {
     if (c->p.storage != storage) continue;
     std::vector<TileItem> items;
-    make_items(c->p.nx, c->p.ny, variant * kNumRows + (c->tile % kNumRows), 0, items);
+    make_items(c->p.nx, c->p.ny, member_tile(c, variant, tile_override), 0, items);
     n += (int)items.size();
   }
   return n;
@@ -428,6 +447,9 @@ int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant) {
 struct lbm_batch {
   std::vector<lbm_ctx*> members;
   BatchEngine eng;
+  void* work = nullptr;
+  size_t work_bytes = 0;
+  int K = 1;
 };
 
 namespace {
@@ -437,14 +459,32 @@ struct BatchShape {
   int items[2];
 };
 
-BatchShape batch_shape(const std::vector<lbm_ctx*>& m) {
+BatchShape batch_shape(const std::vector<lbm_ctx*>& m, int tile_override = -1) {
   BatchShape b{};
   for (int s = 0; s < 2; ++s) {
     b.variants[s] = pick_variant(m, s);
-    b.items[s] = b.variants[s] < 0 ? 0 : count_items(m, s, b.variants[s]);
+    if (b.variants[s] >= 0 && tile_override >= 0) b.variants[s] = tile_variant(tile_override);
+    b.items[s] = b.variants[s] < 0 ? 0 : count_items(m, s, b.variants[s], tile_override);
   }
   return b;
 }
+
+// Rebuilds a batch's engine for a tile override (-1: members' own tiles).
+lbm_status batch_rebuild(lbm_batch* b, int tile_override, int nsub_init) {
+  SCLBM_HIP(hipStreamSynchronize(b->eng.stream));
+  hipStream_t st = b->eng.stream;
+  b->eng.destroy();
+  b->eng = BatchEngine();
+  b->eng.tile_override = tile_override;
+  const BatchShape shape = batch_shape(b->members, tile_override);
+  lbm_status r = b->eng.init(st, b->K, (int)b->members.size(), shape.items, shape.variants,
+                             b->work, b->work_bytes);
+  if (r == LBM_OK) r = b->eng.load(b->members, std::vector<int64_t>(b->members.size(), 0), nsub_init);
+  return r;
+}
+
+// Largest item counts over every tile shape (64-column strips, 8-row bands).
+BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) { return batch_shape(m, 0); }
 
 }  // namespace
 
@@ -688,8 +728,8 @@ lbm_status lbm_batch_work_bytes(lbm_ctx* const* ctxs, int32_t n, size_t* bytes) 
   std::vector<lbm_ctx*> m(ctxs, ctxs + n);
   for (lbm_ctx* c : m)
     if (!c) return fail(LBM_EINVAL, "NULL context in batch");
-  const BatchShape b = batch_shape(m);
-  *bytes = BatchEngine::work_bytes(n, b.items);
+  const BatchShape b = batch_shape_max(m);
+  *bytes = BatchEngine::work_bytes(n, b.items, kMaxGraphSteps);
   return LBM_OK;
 }
 
@@ -698,8 +738,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* work, size_t 
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
   if (!ctxs || n < 1 || !work) return fail(LBM_EINVAL, "bad batch arguments");
-  if (steps_per_graph < 1 || steps_per_graph > 4096)
-    return fail(LBM_EINVAL, "steps_per_graph must be in [1, 4096]");
+  if (steps_per_graph < 1 || steps_per_graph > kMaxGraphSteps)
+    return fail(LBM_EINVAL, "steps_per_graph must be in [1, " + std::to_string(kMaxGraphSteps) + "]");
   if ((uintptr_t)work & 255) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
   std::vector<lbm_ctx*> m(ctxs, ctxs + n);
   for (size_t i = 0; i < m.size(); ++i) {
@@ -713,6 +753,9 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* work, size_t 
   lbm_batch* b = new (std::nothrow) lbm_batch();
   if (!b) return fail(LBM_ENOMEM, "host allocation failed");
   b->members = m;
+  b->work = work;
+  b->work_bytes = work_bytes;
+  b->K = steps_per_graph;
   lbm_status st = b->eng.init(m[0]->stream, steps_per_graph, n, shape.items, shape.variants, work,
                               work_bytes);
   if (st == LBM_OK) st = b->eng.load(m, std::vector<int64_t>(m.size(), 0));
@@ -738,6 +781,59 @@ lbm_status lbm_batch_step_n(lbm_batch* b, int64_t n) {
     c->steps += n;
     c->parity = (int)((c->parity + n) & 1);
   }
+  return LBM_OK;
+}
+
+lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+  hipEvent_t e0, e1;
+  SCLBM_HIP(hipEventCreate(&e0));
+  SCLBM_HIP(hipEventCreate(&e1));
+  int best = -1;
+  double best_ms = 1e300;
+  lbm_status st = LBM_OK;
+  for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+    // Every member takes one step per launch from its current buffer into its
+    // idle one and the descriptors are not advanced: the state is unchanged.
+    st = batch_rebuild(b, k, 1);
+    if (st == LBM_ENOMEM) {  // this shape's tables do not fit the workspace
+      st = LBM_OK;
+      continue;
+    }
+    if (st != LBM_OK) break;
+    BatchEngine& g = b->eng;
+    auto launch_all = [&]() {
+      hipError_t e = hipSuccess;
+      for (int s = 0; s < 2 && e == hipSuccess; ++s)
+        if (g.grid[s] > 0)
+          e = launch_step(s, g.variant[s], g.d_desc, g.d_items[s], g.d_nitems[s], g.grid[s], 0,
+                          g.stream);
+      return e;
+    };
+    hipError_t e = launch_all();
+    if (e == hipSuccess) e = hipEventRecord(e0, g.stream);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_all();
+    if (e == hipSuccess) e = hipEventRecord(e1, g.stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "batch autotune launch");
+      break;
+    }
+    if (ms / reps < best_ms) {
+      best_ms = ms / reps;
+      best = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == LBM_OK && best < 0) st = fail(LBM_ENOMEM, "no tile shape fits the batch workspace");
+  const lbm_status r = batch_rebuild(b, st == LBM_OK ? best : -1, 0);
+  if (st != LBM_OK) return st;
+  if (r != LBM_OK) return r;
+  if (best_out) *best_out = best;
   return LBM_OK;
 }
 

@@ -62,6 +62,13 @@ struct BatchEngine {
   int K = 1, cap_inst = 0;
   int cap_items[2] = {0, 0}, variant[2] = {-1, -1}, grid[2] = {0, 0}, nitems[2] = {0, 0};
   InstDesc* d_desc = nullptr;
+  int* d_counters = nullptr;  // 2 K work counters, zeroed by the tick-begin kernel
+  // Grid sized to the resident capacity, looping over the items (needed when
+  // the item count changes between replays), instead of one workgroup per item.
+  bool persistent = false;
+  // Items taken from the work counters instead of the static order that keeps
+  // neighbouring bands on one XCD.
+  bool dynamic = false;
   int* d_nitems[2] = {nullptr, nullptr};
   TileItem* d_items[2] = {nullptr, nullptr};
   InstDesc* h_desc = nullptr;
@@ -72,11 +79,15 @@ struct BatchEngine {
   hipGraphExec_t exec = nullptr;
   std::vector<lbm_ctx*> members;
 
-  static size_t work_bytes(int cap_inst, const int cap_items[2]);
+  static size_t work_bytes(int cap_inst, const int cap_items[2], int K);
   lbm_status init(hipStream_t st, int steps_per_tick, int cap_inst, const int cap_items[2],
                   const int variants[2], void* work, size_t wbytes);
-  // Uploads the members' descriptors (with `remaining` steps each) and tiles.
-  lbm_status load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining);
+  // Tile used for every member instead of the members' own (-1: none).
+  int tile_override = -1;
+  // Uploads the members' descriptors (with `remaining` steps each, and nsub
+  // sub-steps enabled before any tick) and tiles.
+  lbm_status load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining,
+                  int nsub_init = 0);
   // Sets every member's remaining steps on the device.
   lbm_status arm(int64_t steps);
   // One replay: each member takes min(K, remaining) steps.
@@ -84,8 +95,9 @@ struct BatchEngine {
   void destroy();
 };
 
+int member_tile(const lbm_ctx* c, int variant, int tile_override);
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage);
-int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant);
+int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override);
 
 }  // namespace sclbm
 

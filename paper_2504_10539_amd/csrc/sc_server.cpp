@@ -475,12 +475,14 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
     const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
                                           1u << 22);
     const int cap_items[2] = {per, per};
-    const int variants[2] = {v, v};
-    eng_bytes = align_up(BatchEngine::work_bytes(opts->max_slots, cap_items), 256);
+    const int v16 = tile_variant(default_tile(lbm_params{2048, 2048, -5.0, 1.0, 1, 1.0}));
+    const int variants[2] = {v, v16};
+    eng_bytes = align_up(BatchEngine::work_bytes(opts->max_slots, cap_items, opts->steps_per_tick), 256);
     if (eng_bytes >= pool_bytes / 2) {
       delete s;
       return fail(LBM_ENOMEM, "pool too small for the batch tables");
     }
+    s->eng.persistent = true;
     lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, cap_items,
                                variants, s->pool + pool_bytes - eng_bytes, eng_bytes);
     if (r != LBM_OK) {

@@ -122,6 +122,7 @@ _PROTOS = {
     "lbm_batch_work_bytes": (_i32, [_P(_vp), _i32, _P(_sz)]),
     "lbm_batch_create": (_i32, [_P(_vp), _i32, _vp, _sz, _i32, _P(_vp)]),
     "lbm_batch_step_n": (_i32, [_vp, _i64]),
+    "lbm_batch_autotune": (_i32, [_vp, _i32, _P(_i32)]),
     "lbm_batch_destroy": (_i32, [_vp]),
     "lbm_server_create": (_i32, [_vp, _sz, _vp, _P(lbm_server_opts), _P(_vp)]),
     "lbm_submit": (_i32, [_vp, _P(lbm_request), _P(ctypes.c_uint64)]),
@@ -209,6 +210,27 @@ def _drops_array(drops):
     return d, d.ctypes.data_as(_P(ctypes.c_double))
 
 
+def buffer_bytes(nx: int, ny: int, storage: int = LBM_F32) -> tuple[int, int]:
+    """(bytes of each population buffer, workspace bytes) of one run."""
+    p = make_params(nx, ny, -5.0, 1.0, storage, 1.0)
+    pop, work = _sz(), _sz()
+    _check(LIB.lbm_buffer_bytes(ctypes.byref(p), ctypes.byref(pop), ctypes.byref(work)),
+           "lbm_buffer_bytes")
+    return pop.value, work.value
+
+
+def carve(pool, sizes):
+    """Consecutive 256-byte aligned byte views of one pool tensor, one per size."""
+    out, off = [], 0
+    for n in sizes:
+        off = (off + 255) // 256 * 256
+        if off + n > pool.numel():
+            raise ValueError("pool too small")
+        out.append(pool[off:off + n])
+        off += n
+    return out
+
+
 def tiles() -> list[dict]:
     out = []
     for k in range(LIB.lbm_tile_count()):
@@ -224,16 +246,24 @@ class Simulation:
     """One run: two population buffers and a workspace as torch tensors."""
 
     def __init__(self, nx: int, ny: int, G: float, tau: float, storage: int = LBM_F32,
-                 rho0: float = 0.0, device="cuda", stream=None):
+                 rho0: float = 0.0, device="cuda", stream=None, buffers=None):
+        """`buffers` = (popA, popB, work) device tensors to borrow (e.g. views of
+        one pool, see `carve`); allocated here when omitted."""
         torch = _torch()
         self.params = make_params(nx, ny, G, tau, storage, rho0)
         pop, work = _sz(), _sz()
         _check(LIB.lbm_buffer_bytes(ctypes.byref(self.params), ctypes.byref(pop),
                                     ctypes.byref(work)), "lbm_buffer_bytes")
         self.device = torch.device(device)
-        self.popA = _bytes_tensor(pop.value, self.device)
-        self.popB = _bytes_tensor(pop.value, self.device)
-        self.work = _bytes_tensor(work.value, self.device)
+        if buffers is None:
+            self.popA = _bytes_tensor(pop.value, self.device)
+            self.popB = _bytes_tensor(pop.value, self.device)
+            self.work = _bytes_tensor(work.value, self.device)
+        else:
+            self.popA, self.popB, self.work = buffers
+            self.device = self.popA.device
+        for t in (self.popA, self.popB, self.work):
+            assert t.is_cuda and t.is_contiguous() and t.data_ptr() % 256 == 0
         self.stream = stream
         h = _vp()
         _check(LIB.lbm_create(ctypes.byref(self.params), _dev_ptr(self.popA), _dev_ptr(self.popB),
@@ -338,6 +368,12 @@ class Batch:
     def step(self, n: int):
         _check(LIB.lbm_batch_step_n(self.handle, int(n)), "lbm_batch_step_n")
         return self
+
+    def autotune(self, reps: int = 3) -> int:
+        best = _i32()
+        _check(LIB.lbm_batch_autotune(self.handle, int(reps), ctypes.byref(best)),
+               "lbm_batch_autotune")
+        return best.value
 
     def close(self):
         if getattr(self, "handle", None):

@@ -85,3 +85,27 @@ def test_sweep_512_instances_sampled_against_oracle():
     assert not np.isfinite(oracle.density(ref0)).all()
     assert sims[0].metrics()["finite"] == 0
     b.close()
+
+
+def test_batch_autotune_keeps_state_and_results():
+    """The batch autotuner leaves every member's state untouched and the tuned
+    batch still matches solo runs bitwise; members' own tiles are unchanged."""
+    sims = [_make(c, k) for k, c in enumerate(CASES[:4])]
+    solo = [_make(c, k) for k, c in enumerate(CASES[:4])]
+    tiles_before = [s.tile for s in sims]
+    b = lbm().Batch(sims, steps_per_graph=8)
+    before = [to_np(s.get_state()) for s in sims]
+    best = b.autotune(reps=1)
+    assert 0 <= best < len(lbm().tiles())
+    for s, f in zip(sims, before):
+        assert np.array_equal(to_np(s.get_state()), f)
+    b.step(21)
+    for s in solo:
+        s.step(21)
+    for a, s in zip(sims, solo):
+        assert np.array_equal(to_np(a.get_state()), to_np(s.get_state()))
+    b.close()
+    assert [s.tile for s in sims] == tiles_before
+    sims[0].step(3)
+    solo[0].step(3)
+    assert np.array_equal(to_np(sims[0].get_state()), to_np(solo[0].get_state()))
