@@ -112,7 +112,7 @@ struct Strip {
 
   // Pre-collision populations of the row at march position j for every live
   // slot: f_i(x, y) = A_i(x - e_i), so population i is read from row y - e_iy.
-  __device__ __forceinline__ void pull(int j, float (&f)[CPT + 1][9]) const {
+  __device__ __forceinline__ void pull(int j, float (&f)[CPT + 1][10]) const {
     const int y = row_of(j);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
     const gptr<const T> p0 = in_row(0, y), p1 = in_row(1, y), p2 = in_row(2, ym),
@@ -137,21 +137,24 @@ struct Strip {
   }
 
   // psi of march position j into ring slot (j + 1) & 3 (LDS column index =
-  // strip column + 1).
-  __device__ __forceinline__ void publish(int j, const float (&f)[CPT + 1][9],
+  // strip column + 1); the density is kept in slot 9 for the collision.
+  __device__ __forceinline__ void publish(int j, float (&f)[CPT + 1][10],
                                           float (*ring)[SW + 2]) const {
     float* row = ring[(j + 1) & 3];
     const int t = threadIdx.x;
 #pragma unroll
     for (int k = 0; k < CPT; ++k)
-      if (live[k]) row[t + k * NT + 1] = psi_of(density(f[k]));
+      if (live[k]) {
+        f[k][9] = density(f[k]);
+        row[t + k * NT + 1] = psi_of(f[k][9]);
+      }
     if (live[CPT]) row[t == 0 ? 0 : wcols + 1] = psi_of(density(f[CPT]));
   }
 
   // Collide the row at march position r (psi of positions r-1, r, r+1 already
   // in the ring) and store it.  Marching upwards, the previous position is
   // the row above (y + 1) and the next one the row below.
-  __device__ __forceinline__ void finish(int r, float (&f)[CPT + 1][9],
+  __device__ __forceinline__ void finish(int r, float (&f)[CPT + 1][10],
                                          const float (*ring)[SW + 2]) const {
     const float* prev = ring[r & 3];
     const float* md = ring[(r + 1) & 3];
@@ -170,8 +173,7 @@ struct Strip {
       float Fx, Fy;
       force_of(md[c], md[c + 1], up[c], md[c - 1], dn[c], up[c + 1], up[c - 1], dn[c - 1],
                dn[c + 1], G, Fx, Fy);
-      const float rho = density(f[k]);
-      collide(f[k], rho, Fx, Fy, tau, omega);
+      collide(f[k], f[k][9], Fx, Fy, tau, omega);
       const uint32_t xb = (uint32_t)xc[k] * (uint32_t)sizeof(T);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
@@ -211,7 +213,7 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
     s.setup(dp, ti, sub);
     const int h = s.h;
     if constexpr (PF == 1) {
-      float a[CPT + 1][9], b[CPT + 1][9];
+      float a[CPT + 1][10], b[CPT + 1][10];
       s.pull(-1, a);
       s.publish(-1, a, ring);
       s.pull(0, a);
@@ -230,7 +232,7 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
         if (++r >= h) break;
       }
     } else {
-      float a[CPT + 1][9], b[CPT + 1][9], c[CPT + 1][9];
+      float a[CPT + 1][10], b[CPT + 1][10], c[CPT + 1][10];
       s.pull(-1, a);
       s.publish(-1, a, ring);
       s.pull(0, a);
@@ -259,6 +261,312 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
     }
     __syncthreads();  // the next item reuses the ring (and next_item)
     if (grab) {
+      if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
+      __syncthreads();
+      it = next_item;
+    } else {
+      it += gridDim.x;
+    }
+  }
+}
+
+// ============================================================== paired-column step kernel
+//
+// Wave-local variant of the same step.  Each lane loads one aligned pair of
+// adjacent cells per population (32 bits for FP16 storage, 64 for FP32), so a
+// wavefront moves twice the bytes per memory instruction.  The pulled values
+// shifted by one column come from the neighbouring lane (shuffles) instead of
+// misaligned loads, and the psi rows stay in registers: no LDS, no barrier.
+// A wavefront covers 128 consecutive columns (mod nx) starting two columns
+// left of its 124-column output segment; lanes 0 and 63 only supply the
+// halo.  Needs nx even and nx >= 128, so every pair is aligned and a wave
+// never wraps onto itself.
+
+constexpr int kPairOut = 124;  // output columns per wavefront
+
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1): lane l receives
+// the value of lane l - 1 (from_prev) or l + 1 (from_next); the lane with no
+// source (0, resp. 63) receives zero and is a halo lane whose result is not
+// used.
+__device__ __forceinline__ uint32_t lane_from_prev(uint32_t v) {
+  return __builtin_amdgcn_update_dpp(0u, v, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t lane_from_next(uint32_t v) {
+  return __builtin_amdgcn_update_dpp(0u, v, 0x130, 0xf, 0xf, true);
+}
+__device__ __forceinline__ float lane_from_prev(float v) {
+  return __builtin_bit_cast(float, lane_from_prev(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ float lane_from_next(float v) {
+  return __builtin_bit_cast(float, lane_from_next(__builtin_bit_cast(uint32_t, v)));
+}
+
+// float(half) + s rounded once, the half taken from the low or the high 16
+// bits of w: one mixed-precision FMA (h * 1 + s) instead of a conversion and
+// an add.  The product is exact, so the result equals float(h) + s.
+__device__ __forceinline__ float half_lo_plus(uint32_t w, float s) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
+  return r;
+}
+__device__ __forceinline__ float half_hi_plus(uint32_t w, float s) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(r) : "v"(w), "v"(s));
+  return r;
+}
+
+// Per-storage access to one lane's pair word: the two cells (lo = left,
+// hi = right), the right cell of the previous lane's pair and the left cell
+// of the next lane's pair.
+template <class S>
+struct PairIO;
+
+template <>
+struct PairIO<StoreF32> {
+  using W = uint64_t;
+  __device__ static __forceinline__ float lo(W w, float) {
+    return __builtin_bit_cast(float, (uint32_t)w);
+  }
+  __device__ static __forceinline__ float hi(W w, float) {
+    return __builtin_bit_cast(float, (uint32_t)(w >> 32));
+  }
+  __device__ static __forceinline__ float hi_of_prev(W w, float) {
+    return __builtin_bit_cast(float, lane_from_prev((uint32_t)(w >> 32)));
+  }
+  __device__ static __forceinline__ float lo_of_next(W w, float) {
+    return __builtin_bit_cast(float, lane_from_next((uint32_t)w));
+  }
+  __device__ static __forceinline__ W make(float a, float b, float, float) {
+    return (uint64_t)__builtin_bit_cast(uint32_t, a) |
+           ((uint64_t)__builtin_bit_cast(uint32_t, b) << 32);
+  }
+};
+
+template <>
+struct PairIO<StoreF16S> {
+  using W = uint32_t;
+  __device__ static __forceinline__ float lo(W w, float sh) { return half_lo_plus(w, sh); }
+  __device__ static __forceinline__ float hi(W w, float sh) { return half_hi_plus(w, sh); }
+  __device__ static __forceinline__ float hi_of_prev(W w, float sh) {
+    return half_hi_plus(lane_from_prev(w), sh);
+  }
+  __device__ static __forceinline__ float lo_of_next(W w, float sh) {
+    return half_lo_plus(lane_from_next(w), sh);
+  }
+  __device__ static __forceinline__ W make(float a, float b, float sa, float sb) {
+    const uint16_t ha = __builtin_bit_cast(uint16_t, static_cast<_Float16>(a - sa));
+    const uint16_t hb = __builtin_bit_cast(uint16_t, static_cast<_Float16>(b - sb));
+    return (uint32_t)ha | ((uint32_t)hb << 16);
+  }
+};
+
+// psi of one row around a lane's pair (left neighbour, the two cells, right
+// neighbour) and the densities of the two cells.
+struct PsiRow {
+  float l, a, b, r;
+  float rho_a, rho_b;
+};
+
+template <class S>
+struct PairStrip {
+  using T = typename S::T;
+  using IO = PairIO<S>;
+  using W = typename IO::W;
+
+  uint64_t src, dst;
+  float sh[9];
+  int nx, ny, y0, h, dir;
+  uint32_t pb;  // byte offset of this lane's pair within a row
+  bool out_ok;  // this lane writes its pair
+  float G, tau, omega;
+
+  __device__ __forceinline__ static uint64_t uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+  }
+  // The lane offset re-materialised where it is used, so that the address is
+  // formed as scalar row base + 32-bit lane offset inside the loop body
+  // (global_* with saddr) rather than from a hoisted 64-bit vector offset.
+  __device__ __forceinline__ uint32_t lane_offset() const {
+    uint32_t o = pb;
+    asm volatile("" : "+v"(o));
+    return o;
+  }
+  __device__ __forceinline__ gptr<const W> in_pair(int i, int y, uint32_t o) const {
+    const uint64_t row = uniform(src + row_index(i, y, nx, ny) * sizeof(T));
+    return reinterpret_cast<gptr<const W>>(as_global<const char>(row) + o);
+  }
+  __device__ __forceinline__ gptr<W> out_pair(int i, int y, uint32_t o) const {
+    const uint64_t row = uniform(dst + row_index(i, y, nx, ny) * sizeof(T));
+    return reinterpret_cast<gptr<W>>(as_global<char>(row) + o);
+  }
+
+  __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti, int sub,
+                                        int wave, int lane) {
+    nx = dp->nx;
+    ny = dp->ny;
+    y0 = ti.y0;
+    h = ti.h;
+    dir = ti.dir;
+    G = dp->G;
+    tau = dp->tau;
+    omega = dp->omega;
+    const float rho0 = dp->rho0;
+    const int par = (dp->parity + sub) & 1;
+    const uint64_t a = dp->pop[0], b = dp->pop[1];
+    src = par ? b : a;
+    dst = par ? a : b;
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
+    const int xs = ti.x0 + wave * kPairOut;          // first output column of this wave
+    const int wcols = min(kPairOut, nx - xs);        // output columns (even; may be <= 0)
+    int c = xs - 2 + 2 * lane;                       // first column of the lane's pair
+    c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
+    pb = (uint32_t)c * (uint32_t)sizeof(T);
+    out_ok = lane >= 1 && lane <= 62 && 2 * (lane - 1) < wcols;
+  }
+
+  __device__ __forceinline__ int row_of(int j) const {
+    int y = dir ? y0 + h - 1 - j : y0 + j;
+    return y < 0 ? y + ny : (y >= ny ? y - ny : y);
+  }
+
+  // Raw stored pairs feeding row j: population i comes from row y - e_iy.
+  __device__ __forceinline__ void load(int j, W (&w)[9]) const {
+    const int y = row_of(j);
+    const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+    const uint32_t o = lane_offset();
+    w[0] = *in_pair(0, y, o);
+    w[1] = *in_pair(1, y, o);
+    w[2] = *in_pair(2, ym, o);
+    w[3] = *in_pair(3, y, o);
+    w[4] = *in_pair(4, yp, o);
+    w[5] = *in_pair(5, ym, o);
+    w[6] = *in_pair(6, ym, o);
+    w[7] = *in_pair(7, yp, o);
+    w[8] = *in_pair(8, yp, o);
+  }
+
+  // Pre-collision populations of the pair's two cells and the row's psi.
+  // Populations pulled from x - 1 (e_ix = +1: 1, 5, 8) take the previous
+  // lane's upper cell for cell a; those pulled from x + 1 (e_ix = -1: 3, 6, 7)
+  // take the next lane's lower cell for cell b.
+  __device__ __forceinline__ void expand(const W (&w)[9], float (&fa)[9], float (&fb)[9],
+                                         PsiRow& ps) const {
+    fa[0] = IO::lo(w[0], sh[0]);
+    fb[0] = IO::hi(w[0], sh[0]);
+    fa[2] = IO::lo(w[2], sh[2]);
+    fb[2] = IO::hi(w[2], sh[2]);
+    fa[4] = IO::lo(w[4], sh[4]);
+    fb[4] = IO::hi(w[4], sh[4]);
+    fa[1] = IO::hi_of_prev(w[1], sh[1]);
+    fb[1] = IO::lo(w[1], sh[1]);
+    fa[5] = IO::hi_of_prev(w[5], sh[5]);
+    fb[5] = IO::lo(w[5], sh[5]);
+    fa[8] = IO::hi_of_prev(w[8], sh[8]);
+    fb[8] = IO::lo(w[8], sh[8]);
+    fa[3] = IO::hi(w[3], sh[3]);
+    fb[3] = IO::lo_of_next(w[3], sh[3]);
+    fa[6] = IO::hi(w[6], sh[6]);
+    fb[6] = IO::lo_of_next(w[6], sh[6]);
+    fa[7] = IO::hi(w[7], sh[7]);
+    fb[7] = IO::lo_of_next(w[7], sh[7]);
+    ps.rho_a = density(fa);
+    ps.rho_b = density(fb);
+    ps.a = psi_of(ps.rho_a);
+    ps.b = psi_of(ps.rho_b);
+    ps.l = lane_from_prev(ps.b);
+    ps.r = lane_from_next(ps.a);
+  }
+
+  // Collide the pair at march position r and store it.  Marching upwards the
+  // previous position is the row above.
+  __device__ __forceinline__ void finish(int r, float (&fa)[9], float (&fb)[9], const PsiRow& prev,
+                                         const PsiRow& md, const PsiRow& next) const {
+    const PsiRow& dn = dir ? next : prev;
+    const PsiRow& up = dir ? prev : next;
+    float Fx, Fy;
+    force_of(md.a, md.b, up.a, md.l, dn.a, up.b, up.l, dn.l, dn.b, G, Fx, Fy);
+    collide(fa, md.rho_a, Fx, Fy, tau, omega);
+    force_of(md.b, md.r, up.b, md.a, dn.b, up.r, up.a, dn.a, dn.r, G, Fx, Fy);
+    collide(fb, md.rho_b, Fx, Fy, tau, omega);
+    if (out_ok) {
+      const int y = row_of(r);
+      const uint32_t o = lane_offset();
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        const W v = IO::make(fa[i], fb[i], sh[i], sh[i]);
+        if constexpr (S::kStream)
+          __builtin_nontemporal_store(v, out_pair(i, y, o));
+        else
+          *out_pair(i, y, o) = v;
+      }
+    }
+  }
+};
+
+template <class S, int NW, int PF>
+__global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restrict__ descs,
+                                                       const TileItem* __restrict__ items,
+                                                       const int* __restrict__ nitems_p, int sub,
+                                                       int* __restrict__ grab) {
+  using St = PairStrip<S>;
+  using W = typename St::W;
+  __shared__ int next_item;
+  const int nitems = *nitems_p;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int it = blockIdx.x;
+  if (grab) {
+    if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
+    __syncthreads();
+    it = next_item;
+  }
+  for (; it < nitems;) {
+    const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
+    const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
+    if (sub < dp->nsub && ti.x0 + wave * kPairOut < dp->nx) {
+      St s;
+      s.setup(dp, ti, sub, wave, lane);
+      const int h = s.h;
+      W w0[9], w1[9];
+      float fa0[9], fb0[9], fa1[9], fb1[9];
+      PsiRow p0, p1, p2;
+      s.load(-1, w0);
+      s.expand(w0, fa0, fb0, p0);  // halo row: psi only
+      s.load(0, w0);
+      if constexpr (PF == 2) s.load(1, w1);
+      s.expand(w0, fa0, fb0, p1);
+      // One march position: the row r held in (fa, fb) with psi pm is
+      // collided once the next row (into (fn, gn), psi pn) is expanded.
+      // The roles rotate with period 2 for the populations and 3 for the
+      // psi rows, so six positions per turn need no register copies.
+      int r = 0;
+      auto pos = [&](float(&fa)[9], float(&fb)[9], float(&fn)[9], float(&gn)[9],
+                     W(&wn)[9], W(&wl)[9], PsiRow& pp, PsiRow& pm, PsiRow& pn) -> bool {
+        if constexpr (PF == 2) {
+          // wn: loads of row r + 1 already in flight; wl: free for row r + 2
+          if (r + 2 <= h) s.load(r + 2, wl);
+          s.expand(wn, fn, gn, pn);
+        } else {
+          s.load(r + 1, wn);
+          s.expand(wn, fn, gn, pn);
+        }
+        s.finish(r, fa, fb, pp, pm, pn);
+        return ++r >= h;
+      };
+      while (true) {
+        if (pos(fa0, fb0, fa1, fb1, w1, w0, p0, p1, p2)) break;
+        if (pos(fa1, fb1, fa0, fb0, w0, w1, p1, p2, p0)) break;
+        if (pos(fa0, fb0, fa1, fb1, w1, w0, p2, p0, p1)) break;
+        if (pos(fa1, fb1, fa0, fb0, w0, w1, p0, p1, p2)) break;
+        if (pos(fa0, fb0, fa1, fb1, w1, w0, p1, p2, p0)) break;
+        if (pos(fa1, fb1, fa0, fb0, w0, w1, p2, p0, p1)) break;
+      }
+    }
+    if (grab) {
+      __syncthreads();
       if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
       __syncthreads();
       it = next_item;
@@ -665,6 +973,19 @@ const void* step_fn_t() {
   return reinterpret_cast<const void*>(&k_step<S, NT, CPT, PF>);
 }
 
+template <class S, int NW, int PF>
+hipError_t launch_pair_t(const InstDesc* descs, const TileItem* items, const int* nitems,
+                         int grid, int sub, hipStream_t st) {
+  hipLaunchKernelGGL((k_step_pair<S, NW, PF>), dim3(grid), dim3(64 * NW), 0, st, descs, items,
+                     nitems, sub, (int*)nullptr);
+  return hipGetLastError();
+}
+
+template <class S, int NW, int PF>
+const void* pair_fn_t() {
+  return reinterpret_cast<const void*>(&k_step_pair<S, NW, PF>);
+}
+
 using StepLauncher = hipError_t (*)(const InstDesc*, const TileItem*, const int*, int, int,
                                     hipStream_t);
 using StepFn = const void* (*)();
@@ -676,17 +997,28 @@ using StepFn = const void* (*)();
   X(256, 1, 1) X(256, 1, 2) X(256, 2, 1) X(512, 1, 1) X(512, 1, 2) X(256, 2, 2)         \
   X(1024, 1, 1)
 
-#define SCLBM_AS_VARIANT(NT, CPT, PF) StepVariant{NT, CPT, PF},
+// Paired-column variants (wavefronts per workgroup, rows in flight).
+#define SCLBM_PAIR_VARIANTS(X) X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(4, 1) X(4, 2)
+
+#define SCLBM_AS_VARIANT(NT, CPT, PF) StepVariant{NT, CPT, PF, 0},
 #define SCLBM_AS_LAUNCH(NT, CPT, PF) launch_step_t<S, NT, CPT, PF>,
 #define SCLBM_AS_FN(NT, CPT, PF) step_fn_t<S, NT, CPT, PF>,
-constexpr StepVariant kVariants[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_VARIANT)};
+#define SCLBM_PAIR_AS_VARIANT(NW, PF) StepVariant{64 * NW, 2, PF, 1},
+#define SCLBM_PAIR_AS_LAUNCH(NW, PF) launch_pair_t<S, NW, PF>,
+#define SCLBM_PAIR_AS_FN(NW, PF) pair_fn_t<S, NW, PF>,
+constexpr StepVariant kVariants[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_VARIANT)
+                                         SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_VARIANT)};
 template <class S>
-constexpr StepLauncher kLaunch[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_LAUNCH)};
+constexpr StepLauncher kLaunch[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_LAUNCH)
+                                        SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_LAUNCH)};
 template <class S>
-constexpr StepFn kFn[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_FN)};
+constexpr StepFn kFn[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_FN) SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_FN)};
 #undef SCLBM_AS_VARIANT
 #undef SCLBM_AS_LAUNCH
 #undef SCLBM_AS_FN
+#undef SCLBM_PAIR_AS_VARIANT
+#undef SCLBM_PAIR_AS_LAUNCH
+#undef SCLBM_PAIR_AS_FN
 
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 

@@ -9,12 +9,16 @@
 
 namespace sclbm {
 
-// Step-kernel variants: NT threads per workgroup, CPT cells per thread (strip
-// width NT * CPT), PF rows of loads in flight.
+// Step-kernel variants: NT threads per workgroup, CPT cells per thread, PF
+// rows of loads in flight.  Marching-strip variants (paired = 0) cover
+// NT * CPT columns per workgroup; paired-column variants (paired = 1, CPT = 2)
+// cover kPairColumns per wavefront and need an even nx >= 128.
 struct StepVariant {
-  int threads, cells, prefetch;
+  int threads, cells, prefetch, paired;
 };
-constexpr int kNumVariants = 14;
+constexpr int kNumVariants = 20;
+constexpr int kPairColumns = 124;
+constexpr int kPairMinNx = 128;
 // Band heights a tile shape may use; tile shape k = variant * kNumRows + row index.
 constexpr int kRowChoices[] = {8, 16, 32, 64, 128};
 constexpr int kNumRows = 5;

@@ -421,13 +421,21 @@ int member_tile(const lbm_ctx* c, int variant, int tile_override) {
 }
 
 // Strip variant used for one storage type: that of the widest member's tile.
+// A paired-column variant is kept only if every member of that storage type
+// can run it; otherwise the widest member's default variant is used.
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   int best = -1, bestn = -1;
+  const lbm_ctx* widest = nullptr;
   for (lbm_ctx* c : m)
     if (c->p.storage == storage && c->p.nx > bestn) {
       bestn = c->p.nx;
       best = tile_variant(c->tile);
+      widest = c;
     }
+  if (best < 0) return best;
+  for (lbm_ctx* c : m)
+    if (c->p.storage == storage && !tile_valid(best * kNumRows, c->p.nx))
+      return tile_variant(default_tile(widest->p));
   return best;
 }
 
@@ -542,7 +550,7 @@ lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_by
     return hip_fail(e, "descriptor upload");
   }
   int k = tuned_tile(*p, c->arch);
-  if (k < 0) k = default_tile(*p);
+  if (k < 0 || !tile_valid(k, p->nx)) k = default_tile(*p);
   s = c->upload_tile(k);
   if (s != LBM_OK) {
     delete c;
@@ -660,7 +668,7 @@ lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* 
                              int32_t* prefetch) {
   if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
   const StepVariant& v = step_variant(tile_variant(k));
-  if (width) *width = v.threads * v.cells;
+  if (width) *width = tile_width(k);
   if (rows) *rows = tile_rows(k);
   if (threads) *threads = v.threads;
   if (prefetch) *prefetch = v.prefetch;
@@ -670,6 +678,8 @@ lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* 
 lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
   if (!c) return fail(LBM_EINVAL, "ctx is NULL");
   if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+  if (!tile_valid(k, c->p.nx))
+    return fail(LBM_EINVAL, "paired-column tile shapes need an even nx >= 128");
   if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
   return c->upload_tile(k);
 }
@@ -687,6 +697,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
   double best_ms = 1e300;
   lbm_status st = LBM_OK;
   for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+    if (!tile_valid(k, c->p.nx)) continue;
     st = c->upload_tile(k);
     if (st != LBM_OK) break;
     const int v = tile_variant(k);
@@ -794,6 +805,9 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
   double best_ms = 1e300;
   lbm_status st = LBM_OK;
   for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+    bool valid = true;
+    for (lbm_ctx* c : b->members) valid = valid && tile_valid(k, c->p.nx);
+    if (!valid) continue;
     // Every member takes one step per launch from its current buffer into its
     // idle one and the descriptors are not advanced: the state is unchanged.
     st = batch_rebuild(b, k, 1);

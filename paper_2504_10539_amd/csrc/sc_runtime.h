@@ -31,7 +31,12 @@ inline int tile_variant(int k) { return k / kNumRows; }
 inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }
 inline int tile_width(int k) {
   const StepVariant& v = step_variant(tile_variant(k));
-  return v.threads * v.cells;
+  return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
+}
+// Whether tile shape k can run a grid nx columns wide.
+inline bool tile_valid(int k, int nx) {
+  const StepVariant& v = step_variant(tile_variant(k));
+  return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
 
 // Work items of one grid for tile shape k, appended for simulation `inst`.
