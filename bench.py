@@ -8,15 +8,17 @@ workload: droplet initialisation, `--lbm-steps` (default 5000) fused
 stream-collide-force time steps, FP64 conservation + interface metrics, and
 the moments export, on a 4096 x 4096 periodic grid with 2000 droplets (centres
 uniform, R uniform in [8, 48], max-merged, tanh width 2, noise 1e-3), G = -5.5
-and tau = 1.0 (the paper's Sec. III-A values; tau = 0.8 diverges for this
-field).  Populations are FP32; the arithmetic is FP32.
+and tau = 1.0 (the paper's Sec. III-A values; with tau = 0.8 this field goes
+non-finite within about 100 steps, in the FP64 oracle as on the GPU).
+Populations are FP32; the arithmetic is FP32.
 
 `value` is lattice updates per second (MLUPS) of the whole job with the inputs
 resident; `roofline` prices the step kernel (the dominant kernel) at 72
 algorithmic bytes per lattice update against the 8 TB/s HBM peak, with the
 kernel's average launch time measured by HIP events on its stream over the
-timed region.  Extra objects report the FP16-shifted storage, the batched
-parameter sweep, the serving loop and the FP64 oracle's CPU rate.
+timed region.  Extra objects report the FP16-shifted storage, a 1024^2
+single-droplet run, the batched parameter sweep, the serving loop and the FP64
+oracle's CPU rate.
 """
 from __future__ import annotations
 
@@ -48,18 +50,32 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel_hash: str, key: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None."""
+def traffic_from_profiles(lbm, kernel_hash: str, storage: str, n: int, tile: int):
+    """HBM bytes per launch of the step kernel with this tile shape, from the
+    committed rocprofv3 counter summary; None when the summary has no entry for
+    it or was taken on other kernel sources."""
     path = os.path.join(HERE, "profiles", "step_counters.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    e = d.get(key)
-    if not e or e.get("kernel_hash") != kernel_hash:
-        return None
-    return e.get("bytes_per_launch")
+    t = lbm.tiles()[tile]
+    key = (storage, n, kernel_name(lbm, tile, lbm.LBM_F32 if storage == "f32" else lbm.LBM_F16_SHIFTED),
+           t["width"], t["rows"])
+    for e in d.get("entries", []):
+        if (e.get("storage"), e.get("n"), e.get("kernel"), e.get("width"), e.get("rows")) == key:
+            return e.get("bytes_per_launch") if e.get("kernel_hash") == kernel_hash else None
+    return None
+
+
+def kernel_name(lbm, tile: int, storage: int) -> str:
+    """Name of the step kernel instance that tile shape `tile` launches."""
+    t = lbm.tiles()[tile]
+    st = "StoreF32" if storage == lbm.LBM_F32 else "StoreF16S"
+    if t["paired"]:
+        return f"k_step_pair<{st}, {t['threads'] // 64}, {t['prefetch']}>"
+    return f"k_step<{st}, {t['threads']}, {t['cells']}, {t['prefetch']}>"
 
 
 def run_main(args, torch, lbm, inputs):
@@ -117,6 +133,7 @@ def run_main(args, torch, lbm, inputs):
             "achieved_gbs": achieved,
             "bytes_per_update": bpu,
             "tile": sim.tile,
+            "kernel": kernel_name(lbm, sim.tile, storage),
             "metrics": {k: m[k] for k in ("W", "Gmax", "drho", "W_eff", "E_int", "mass", "finite")},
         }
         log(f"[{name}] {out[name]['mlups']:.0f} MLUPS whole job, step kernel "
@@ -125,6 +142,38 @@ def run_main(args, torch, lbm, inputs):
         del rho, ux, uy
         torch.cuda.empty_cache()
     return out
+
+
+def run_single_droplet(args, torch, lbm, inputs):
+    """One droplet, R = 200, on a 1024^2 grid (G -5.0, tau 1.0), FP32, 10000 steps.
+    A+B are 75.5 MB, so this run is served largely from the Infinity Cache."""
+    n, steps = 1024, args.c2_steps
+    sim = lbm.Simulation(n, n, -5.0, 1.0, lbm.LBM_F32)
+    sim.init_droplets(inputs.single_droplet(n, 200), seed=1)
+    if not args.no_autotune:
+        sim.autotune(reps=8)
+    stream = torch.cuda.current_stream()
+    sim.step(100)
+    sim.init_droplets(inputs.single_droplet(n, 200), seed=1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    m = sim.metrics()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    res = {"workload": "single_droplet_1024", "steps": steps, "mlups": n * n * steps / wall / 1e6,
+           "step_kernel_ms": ms, "step_kernel_mlups": n * n / (ms * 1e-3) / 1e6,
+           "achieved_gbs": BYTES_F32 * n * n / (ms * 1e-3) / 1e9, "tile": sim.tile,
+           "kernel": kernel_name(lbm, sim.tile, lbm.LBM_F32),
+           "metrics": {k: m[k] for k in ("W", "Gmax", "drho", "W_eff", "E_int", "mass", "finite")}}
+    log(f"[single droplet 1024^2] {res['step_kernel_mlups']:.0f} MLUPS per launch, "
+        f"{res['mlups']:.0f} MLUPS whole run")
+    sim.close()
+    torch.cuda.empty_cache()
+    return res
 
 
 def run_copy_reference(torch, lbm):
@@ -253,6 +302,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip sweep, serving and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--c2-steps", type=int, default=10000)
+    ap.add_argument("--only", choices=["single_droplet_1024"], default=None,
+                    help="run one extra workload alone and print its result (for profiling)")
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--sweep-instances", type=int, default=512)
     ap.add_argument("--sweep-steps", type=int, default=4000)
@@ -264,8 +316,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the step would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(independent runs would be placed whole on separate GPUs; one large grid "
+              "would split into y-slabs exchanging halo rows)", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -274,13 +327,16 @@ def main():
         sys.exit(2)
     from paper_2504_10539_amd import inputs, lbm
 
+    if args.only == "single_droplet_1024":
+        print(json.dumps(run_single_droplet(args, torch, lbm, inputs)), flush=True)
+        return
     log(f"device {torch.cuda.get_device_name(0)}; workload {args.n}^2, {args.drops} droplets, "
         f"G {args.G}, tau {args.tau}, {args.lbm_steps} LBM steps per job")
     main_res = run_main(args, torch, lbm, inputs)
     f32 = main_res["f32"]
     khash = kernel_source_hash()
     copy_gbs = run_copy_reference(torch, lbm)
-    traffic = traffic_from_profiles(khash, f"f32_{args.n}")
+    traffic = traffic_from_profiles(lbm, khash, "f32", args.n, f32["tile"])
     line = {
         "metric": "MLUPS & % HBM roofline (FP32 vs FP16-shifted); batched p50/p99 latency",
         "value": round(f32["mlups"], 1),
@@ -301,16 +357,18 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(f32["achieved_gbs"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(f32["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step<StoreF32>",
+                     "traffic": traffic, "kernel": f32["kernel"],
                      "bytes_per_update": BYTES_F32, "launch_ms": round(f32["step_kernel_ms"], 5),
                      "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
         "f32": f32,
     }
     if "f16_shifted" in main_res:
         f16 = main_res["f16_shifted"]
-        f16 = dict(f16, roofline_frac=round(f16["achieved_gbs"] / HBM_PEAK_GBS, 4))
+        f16 = dict(f16, roofline_frac=round(f16["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                   traffic=traffic_from_profiles(lbm, khash, "f16_shifted", args.n, f16["tile"]))
         line["f16_shifted"] = f16
     if not args.no_extras:
+        line["single_droplet_1024"] = run_single_droplet(args, torch, lbm, inputs)
         line["sweep_512x256"] = run_sweep(args, torch, lbm, inputs)
         line["serving"] = run_serving(args, torch, lbm, inputs)
         if not args.no_cpu:

@@ -170,11 +170,16 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
 
 /* Tile shapes of the step kernel.  Shape k (0 <= k < lbm_tile_count()) is a
  * strip of `width` columns marched over `rows` rows by `threads` threads with
- * `prefetch` rows of loads in flight.  Every shape computes bitwise the same
- * result; only speed differs. */
+ * `prefetch` rows of loads in flight, each thread holding `cells` cells of a
+ * row.  paired = 0: the psi halo of a row is shared through LDS (any grid
+ * width).  paired = 1: each lane holds two adjacent cells and takes its
+ * column neighbours from the adjacent lanes of its wavefront; such shapes
+ * need an even nx >= 128 (lbm_set_tile returns LBM_EINVAL otherwise).  Every
+ * shape computes bitwise the same result; only speed differs.  Any output
+ * pointer may be NULL; k out of range is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
-                             int32_t* prefetch);
+                             int32_t* prefetch, int32_t* cells, int32_t* paired);
 lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t k);
 int32_t lbm_get_tile(const lbm_ctx* ctx);
 

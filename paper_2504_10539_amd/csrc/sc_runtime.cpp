@@ -99,13 +99,23 @@ std::vector<TileItem> xcd_order(const std::vector<TileItem>& items) {
   return out;
 }
 
-int default_tile(const lbm_params& p) {
+int default_strip_tile(const lbm_params& p) {
   // variant index * kNumRows + row index; see kVariants / kRowChoices.
   if (p.nx <= 64) return 0 * kNumRows + 0;   // 64 threads, 1 cell, 8 rows
   if (p.nx <= 128) return 2 * kNumRows + 1;  // 128 threads, 16 rows
   if (p.storage == LBM_F16_SHIFTED)
     return 9 * kNumRows + 2;                 // 256 threads x 2 cells, 32 rows
   return 8 * kNumRows + 0;                   // 256 threads, 2 rows in flight, 8 rows
+}
+
+int default_tile(const lbm_params& p) {
+  // FP16-shifted storage: paired columns, 4 wavefronts, 2 rows in flight,
+  // 8-row bands, where the grid allows it.
+  if (p.storage == LBM_F16_SHIFTED) {
+    const int k = find_variant(256, 2, 2, 1) * kNumRows + 0;
+    if (tile_valid(k, p.nx)) return k;
+  }
+  return default_strip_tile(p);
 }
 
 std::string device_arch() {
@@ -422,7 +432,7 @@ int member_tile(const lbm_ctx* c, int variant, int tile_override) {
 
 // Strip variant used for one storage type: that of the widest member's tile.
 // A paired-column variant is kept only if every member of that storage type
-// can run it; otherwise the widest member's default variant is used.
+// can run it; otherwise the widest member's default strip variant is used.
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   int best = -1, bestn = -1;
   const lbm_ctx* widest = nullptr;
@@ -435,7 +445,7 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   if (best < 0) return best;
   for (lbm_ctx* c : m)
     if (c->p.storage == storage && !tile_valid(best * kNumRows, c->p.nx))
-      return tile_variant(default_tile(widest->p));
+      return tile_variant(default_strip_tile(widest->p));
   return best;
 }
 
@@ -665,13 +675,15 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
 int32_t lbm_tile_count(void) { return kNumTiles; }
 
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
-                             int32_t* prefetch) {
+                             int32_t* prefetch, int32_t* cells, int32_t* paired) {
   if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
   const StepVariant& v = step_variant(tile_variant(k));
   if (width) *width = tile_width(k);
   if (rows) *rows = tile_rows(k);
   if (threads) *threads = v.threads;
   if (prefetch) *prefetch = v.prefetch;
+  if (cells) *cells = v.cells;
+  if (paired) *paired = v.paired;
   return LBM_OK;
 }
 

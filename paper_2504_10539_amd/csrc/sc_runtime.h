@@ -33,6 +33,15 @@ inline int tile_width(int k) {
   const StepVariant& v = step_variant(tile_variant(k));
   return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
 }
+// Index of the step variant with these parameters (-1 if there is none).
+inline int find_variant(int threads, int cells, int prefetch, int paired) {
+  for (int v = 0; v < kNumVariants; ++v) {
+    const StepVariant& s = step_variant(v);
+    if (s.threads == threads && s.cells == cells && s.prefetch == prefetch && s.paired == paired)
+      return v;
+  }
+  return -1;
+}
 // Whether tile shape k can run a grid nx columns wide.
 inline bool tile_valid(int k, int nx) {
   const StepVariant& v = step_variant(tile_variant(k));
@@ -52,7 +61,10 @@ struct WorkLayout {
 };
 WorkLayout work_layout(int nx, int ny);
 
+// Default tile shape of a run; default_strip_tile never picks a paired-column
+// variant, so it is valid for every grid width.
 int default_tile(const lbm_params& p);
+int default_strip_tile(const lbm_params& p);
 int tuned_tile(const lbm_params& p, const std::string& arch);  // -1 if none
 void record_tuned_tile(const lbm_params& p, const std::string& arch, int tile, double ms);
 std::string device_arch();

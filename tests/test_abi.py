@@ -102,4 +102,10 @@ def test_tile_table(lbm):
     assert all(t["width"] >= 64 and t["rows"] >= 8 for t in tiles)
     assert len({(t["width"], t["rows"], t["threads"], t["prefetch"]) for t in tiles}) == len(tiles)
     w = ctypes.c_int32()
-    assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None) == lbm.LBM_EINVAL
+    assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None, None,
+                                     None) == lbm.LBM_EINVAL
+    for t in tiles:
+        if t["paired"]:
+            assert t["cells"] == 2 and t["width"] == t["threads"] // 64 * 124
+        else:
+            assert t["width"] == t["threads"] * t["cells"]
