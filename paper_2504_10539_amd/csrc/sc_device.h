@@ -161,8 +161,14 @@ __device__ __forceinline__ void collide(float f[9], float rho, float Fx, float F
   const float ux = fmaf(tau, Fx, jx) * inv;
   const float uy = fmaf(tau, Fy, jy) * inv;
   const float base = fmaf(-1.5f, fmaf(ux, ux, uy * uy), 1.0f);
-  const float r1 = kW1 * rho;
-  const float r2 = kW2 * rho;
+  // w_1 rho and w_5 rho as the correctly rounded quotients rho / 9 and
+  // rho / 36: the estimate kW1 * rho plus one FMA correction with its exact
+  // residual.  The FP32 weights themselves are 7.45e-9 too large, and that
+  // one-signed bias in every moving equilibrium population measurably drifts
+  // the interfaces over thousands of steps.  rho / 36 = (rho / 9) / 4 exactly.
+  const float q9 = kW1 * rho;
+  const float r1 = fmaf(fmaf(-q9, 9.0f, rho), kW1, q9);
+  const float r2 = 0.25f * r1;
   float feq[9];
   {
     const float s = fmaf(4.5f * ux, ux, base), t = 3.0f * ux;
