@@ -1,0 +1,67 @@
+"""The many-droplet error run: the [0, 512)^2 window of the 4096^2 2000-droplet
+field (radii uniform in [8, 48], seed 3), treated as its own periodic domain,
+G = -5.5, tau = 1.0, 5000 steps.  GPU FP32 and FP16-shifted storage against the
+FP64 oracle, errors logged every 500 steps.
+
+Measured (MI355X): FP32 per-cell max |drho|/rho grows to 7.5e-5 by step 5000
+(2.6e-5 of rho_max) and every metric stays within 3e-5.  A numpy FP32
+emulation of the kernel's arithmetic gives errors of the same size (7.0e-6
+against the GPU's 8.1e-6 at step 500), so this is the FP32 arithmetic, not a
+kernel defect; an FP32-ulp perturbation of the FP64 run grows only to 1.8e-6,
+i.e. the field itself does not amplify rounding noise.
+FP16-shifted storage keeps every metric within 0.9%, while the droplets
+drift apart from the FP64 run (per-cell density errors of order one by step
+2000); the density bar does not hold for this workload.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_10539_amd import inputs
+from tests.gpu_helpers import lbm, need_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("W", "Gmax", "drho", "W_eff", "E_int")
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def test_many_droplet_window_error_series(nthreads):
+    L = lbm()
+    n, G, tau = 512, -5.5, 1.0
+    drops = inputs.many_droplets(4096, 2000, 8, 48, seed=3)
+    f = oracle.droplet_state(n, n, drops, seed=3, period=(4096, 4096))
+    sims = {"f32": L.Simulation(n, n, G, tau, L.LBM_F32),
+            "f16": L.Simulation(n, n, G, tau, L.LBM_F16_SHIFTED, 1.0)}
+    for s in sims.values():
+        s.init_droplets(drops, seed=3, period=(4096, 4096))
+    worst = {"f32_cell": 0.0, "f32_range": 0.0, "f32_metric": 0.0, "f16_metric": 0.0}
+    for seg in range(1, 11):
+        f = oracle.step(f, G, tau, 500, nthreads)
+        rr = oracle.density(f)
+        mr = oracle.metrics(rr)
+        line = [f"step {500 * seg}"]
+        for name, s in sims.items():
+            s.step(500)
+            rho = to_np(s.moments()[0])
+            m = s.metrics()
+            assert m["finite"] == 1, (name, seg)
+            cell = float(np.max(np.abs(rho - rr) / rr))
+            rng = float(np.max(np.abs(rho - rr)) / rr.max())
+            met = max(abs(m[k] / mr[k] - 1) for k in KEYS)
+            line.append(f"{name}: cell {cell:.2e} range {rng:.2e} metrics {met:.2e}")
+            if name == "f32":
+                worst["f32_cell"] = max(worst["f32_cell"], cell)
+                worst["f32_range"] = max(worst["f32_range"], rng)
+                worst["f32_metric"] = max(worst["f32_metric"], met)
+            else:
+                worst["f16_metric"] = max(worst["f16_metric"], met)
+        print(" | ".join(line))
+    # regression bounds over the measured series, with margin
+    assert worst["f32_cell"] < 2e-4 and worst["f32_range"] < 6e-5, worst
+    assert worst["f32_metric"] < 1e-4, worst
+    assert worst["f16_metric"] < 0.02, worst
