@@ -143,6 +143,23 @@ lbm_status lbm_init_droplets(lbm_ctx* ctx, const double* drops, int32_t n, const
  * enqueue.  LBM_EBUSY if the context belongs to a live batch. */
 lbm_status lbm_step_n(lbm_ctx* ctx, int64_t n);
 
+/* Advances n >= 0 steps like lbm_step_n and records the interface metrics of
+ * every `every`-th state on the way (the time series of Sec. IV's evolution
+ * runs): the states at step counts t0, t0 + every, ... below t0 + n, where t0
+ * is lbm_step_count at the call, ceil(n / every) records in all, written to
+ * out[0 ..] (host array of `capacity` records; *count receives the number
+ * written).  Each record is computed inside the launch that advances that
+ * state, from the populations it pulls, with the FP64 arithmetic of
+ * lbm_interface_metrics (rho summed in FP64 in index order, Eq. (16) with
+ * periodic wrap): n_above, G_max, rho_max and rho_min equal what
+ * lbm_interface_metrics reports for that state, and the sums agree up to FP64
+ * summation order.  The step itself is bitwise the one lbm_step_n takes.  The
+ * metrics of the final state t0 + n are not included (lbm_interface_metrics
+ * gives them).  Synchronises.  LBM_EINVAL if every < 1 or capacity <
+ * ceil(n / every); LBM_EBUSY for a member of a live batch. */
+lbm_status lbm_step_series(lbm_ctx* ctx, int64_t n, int32_t every, lbm_metrics* out,
+                           int32_t capacity, int32_t* count);
+
 /* Writes the macroscopic fields of the current state into caller device
  * arrays of nx * ny floats: rho = sum_i f_i and the half-force-corrected
  * velocity u = (sum_i f_i e_i + F / 2) / rho.  Any pointer may be NULL.

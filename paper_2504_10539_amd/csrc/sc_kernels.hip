@@ -27,10 +27,17 @@ namespace sclbm {
 // each side (two lanes) and one halo row above and below the band.  PF rows
 // of loads are kept in flight ahead of the row being finished.
 
-template <class S, int NT, int CPT>
+// DIAG = true: the launch also accumulates, from the same pulled populations,
+// the FP64 interface diagnostics of the state it advances (the quantities of
+// the separate diagnostics pass, per cell in the same arithmetic); rho in FP64
+// goes through a second LDS ring for the Eq. (16) gradient.
+template <class S, int NT, int CPT, bool DIAG = false>
 struct Strip {
   using T = typename S::T;
   static constexpr int SW = NT * CPT;
+  static constexpr int kCPT = CPT;
+  static constexpr bool kDiag = DIAG;
+  using RhoRing = double (*)[SW + 2];
 
   uint64_t src, dst;  // buffer base addresses (read / written this step)
   float sh[9];
@@ -39,6 +46,9 @@ struct Strip {
   int xc[CPT + 1], xm[CPT + 1], xp[CPT + 1];
   bool live[CPT + 1];
   float G, tau, omega;
+  // DIAG accumulators: mass, mom_x, mom_y, bad cells, cells above the
+  // threshold, max |grad rho|, sum |grad rho|, sum |grad rho|^2, rho max, min.
+  double acc[10];
 
   // First element of row y of population i.  The address is the same for the
   // whole workgroup; readfirstlane keeps it in scalar registers, so each load
@@ -96,6 +106,15 @@ struct Strip {
     }
   }
 
+  // A lane's byte offset re-materialised where it is used (an empty asm on a
+  // copy), so that each access is formed in the loop body as scalar row base +
+  // 32-bit lane offset (global_* with saddr) instead of from a hoisted 64-bit
+  // vector offset.
+  __device__ __forceinline__ static uint32_t fresh(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+  }
+
   // Element at byte offset `boff` (32-bit, lane-varying) from a uniform row base.
   __device__ __forceinline__ static gptr<const T> at(gptr<const T> base, uint32_t boff) {
     return reinterpret_cast<gptr<const T>>(reinterpret_cast<gptr<const char>>(base) + boff);
@@ -122,7 +141,8 @@ struct Strip {
 #pragma unroll
     for (int k = 0; k <= CPT; ++k) {
       if (live[k]) {
-        const uint32_t c = (uint32_t)xc[k] * B, m = (uint32_t)xm[k] * B, p = (uint32_t)xp[k] * B;
+        const uint32_t c = fresh((uint32_t)xc[k] * B), m = fresh((uint32_t)xm[k] * B),
+                       p = fresh((uint32_t)xp[k] * B);
         f[k][0] = S::load(at(p0, c), sh[0]);
         f[k][1] = S::load(at(p1, m), sh[1]);
         f[k][2] = S::load(at(p2, c), sh[2]);
@@ -138,8 +158,8 @@ struct Strip {
 
   // psi of march position j into ring slot (j + 1) & 3 (LDS column index =
   // strip column + 1); the density is kept in slot 9 for the collision.
-  __device__ __forceinline__ void publish(int j, float (&f)[CPT + 1][10],
-                                          float (*ring)[SW + 2]) const {
+  __device__ __forceinline__ void publish(int j, float (&f)[CPT + 1][10], float (*ring)[SW + 2],
+                                          RhoRing rring = nullptr) const {
     float* row = ring[(j + 1) & 3];
     const int t = threadIdx.x;
 #pragma unroll
@@ -147,20 +167,75 @@ struct Strip {
       if (live[k]) {
         f[k][9] = density(f[k]);
         row[t + k * NT + 1] = psi_of(f[k][9]);
+        if constexpr (DIAG) rring[(j + 1) & 3][t + k * NT + 1] = density64(f[k]);
       }
-    if (live[CPT]) row[t == 0 ? 0 : wcols + 1] = psi_of(density(f[CPT]));
+    if (live[CPT]) {
+      row[t == 0 ? 0 : wcols + 1] = psi_of(density(f[CPT]));
+      if constexpr (DIAG) rring[(j + 1) & 3][t == 0 ? 0 : wcols + 1] = density64(f[CPT]);
+    }
+  }
+
+  // FP64 density: the widened populations summed in index order.
+  __device__ __forceinline__ static double density64(const float (&f)[10]) {
+    double r = 0.0;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r += (double)f[i];
+    return r;
+  }
+
+  __device__ __forceinline__ void diag_zero() {
+#pragma unroll
+    for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+    acc[8] = -INFINITY;
+    acc[9] = INFINITY;
+  }
+
+  // Diagnostics of one cell of position r (its pre-collision populations f,
+  // FP64 rho of rows r-1, r, r+1 in the ring): Eq. (16) with periodic wrap,
+  // threshold of Eq. (9) strict.
+  __device__ __forceinline__ void diag_cell(const float (&f)[10], int c, const double* dn,
+                                            const double* md, const double* up) {
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fin = fin && isfinite(f[i]);
+    const double r = md[c];
+    const double jx = ((double)f[1] - (double)f[3]) + ((double)f[5] - (double)f[6]) +
+                      ((double)f[8] - (double)f[7]);
+    const double jy = ((double)f[2] - (double)f[4]) + ((double)f[5] - (double)f[8]) +
+                      ((double)f[6] - (double)f[7]);
+    const double gx = (md[c + 1] - md[c - 1]) / 2.0;
+    const double gy = (up[c] - dn[c]) / 2.0;
+    const double g = sqrt(gx * gx + gy * gy);
+    acc[0] += r;
+    acc[1] += jx;
+    acc[2] += jy;
+    if (!fin || !(r > 0.0)) acc[3] += 1.0;
+    if (g > 0.01) acc[4] += 1.0;
+    acc[5] = fmax(acc[5], g);
+    acc[6] += g;
+    acc[7] += g * g;
+    acc[8] = fmax(acc[8], r);
+    acc[9] = fmin(acc[9], r);
   }
 
   // Collide the row at march position r (psi of positions r-1, r, r+1 already
   // in the ring) and store it.  Marching upwards, the previous position is
   // the row above (y + 1) and the next one the row below.
-  __device__ __forceinline__ void finish(int r, float (&f)[CPT + 1][10],
-                                         const float (*ring)[SW + 2]) const {
+  __device__ __forceinline__ void finish(int r, float (&f)[CPT + 1][10], const float (*ring)[SW + 2],
+                                         RhoRing rring = nullptr) {
     const float* prev = ring[r & 3];
     const float* md = ring[(r + 1) & 3];
     const float* next = ring[(r + 2) & 3];
     const float* dn = dir ? next : prev;
     const float* up = dir ? prev : next;
+    if constexpr (DIAG) {
+      const double* rp = rring[r & 3];
+      const double* rn = rring[(r + 2) & 3];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k)
+        if (live[k])
+          diag_cell(f[k], threadIdx.x + k * NT + 1, dir ? rn : rp, rring[(r + 1) & 3], dir ? rp : rn);
+    }
     gptr<T> o[9];
     const int y = row_of(r);
 #pragma unroll
@@ -174,7 +249,7 @@ struct Strip {
       force_of(md[c], md[c + 1], up[c], md[c - 1], dn[c], up[c + 1], up[c - 1], dn[c - 1],
                dn[c + 1], G, Fx, Fy);
       collide(f[k], f[k][9], Fx, Fy, tau, omega);
-      const uint32_t xb = (uint32_t)xc[k] * (uint32_t)sizeof(T);
+      const uint32_t xb = fresh((uint32_t)xc[k] * (uint32_t)sizeof(T));
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         if constexpr (S::kStream)
@@ -185,6 +260,61 @@ struct Strip {
     }
   }
 };
+
+// One band of a strip: PF rows of loads in flight ahead of the row being
+// finished; one barrier per row.
+template <class St, int PF>
+__device__ __forceinline__ void march(St& s, float (*ring)[St::SW + 2],
+                                      typename St::RhoRing rring = nullptr) {
+  const int h = s.h;
+  constexpr int C1 = St::kCPT + 1;  // the lane's cells plus its halo slot
+  if constexpr (PF == 1) {
+    float a[C1][10], b[C1][10];
+    s.pull(-1, a);
+    s.publish(-1, a, ring, rring);
+    s.pull(0, a);
+    s.publish(0, a, ring, rring);
+    int r = 0;
+    while (true) {
+      s.pull(r + 1, b);
+      s.publish(r + 1, b, ring, rring);
+      __syncthreads();
+      s.finish(r, a, ring, rring);
+      if (++r >= h) break;
+      s.pull(r + 1, a);
+      s.publish(r + 1, a, ring, rring);
+      __syncthreads();
+      s.finish(r, b, ring, rring);
+      if (++r >= h) break;
+    }
+  } else {
+    float a[C1][10], b[C1][10], c[C1][10];
+    s.pull(-1, a);
+    s.publish(-1, a, ring, rring);
+    s.pull(0, a);
+    s.pull(1, b);
+    s.publish(0, a, ring, rring);
+    int r = 0;
+    // a: row r (published); b: row r + 1 (in flight)
+    while (true) {
+      if (r + 2 <= h) s.pull(r + 2, c);
+      s.publish(r + 1, b, ring, rring);
+      __syncthreads();
+      s.finish(r, a, ring, rring);
+      if (++r >= h) break;
+      if (r + 2 <= h) s.pull(r + 2, a);
+      s.publish(r + 1, c, ring, rring);
+      __syncthreads();
+      s.finish(r, b, ring, rring);
+      if (++r >= h) break;
+      if (r + 2 <= h) s.pull(r + 2, b);
+      s.publish(r + 1, a, ring, rring);
+      __syncthreads();
+      s.finish(r, c, ring, rring);
+      if (++r >= h) break;
+    }
+  }
+}
 
 // Work distribution: with grab == nullptr workgroup b takes items b, b + grid,
 // ...; otherwise each workgroup takes the next item from the counter *grab
@@ -209,55 +339,9 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
     if (sub < dp->nsub) {
-    St s;
-    s.setup(dp, ti, sub);
-    const int h = s.h;
-    if constexpr (PF == 1) {
-      float a[CPT + 1][10], b[CPT + 1][10];
-      s.pull(-1, a);
-      s.publish(-1, a, ring);
-      s.pull(0, a);
-      s.publish(0, a, ring);
-      int r = 0;
-      while (true) {
-        s.pull(r + 1, b);
-        s.publish(r + 1, b, ring);
-        __syncthreads();
-        s.finish(r, a, ring);
-        if (++r >= h) break;
-        s.pull(r + 1, a);
-        s.publish(r + 1, a, ring);
-        __syncthreads();
-        s.finish(r, b, ring);
-        if (++r >= h) break;
-      }
-    } else {
-      float a[CPT + 1][10], b[CPT + 1][10], c[CPT + 1][10];
-      s.pull(-1, a);
-      s.publish(-1, a, ring);
-      s.pull(0, a);
-      s.pull(1, b);
-      s.publish(0, a, ring);
-      int r = 0;
-      // a: row r (published); b: row r + 1 (in flight)
-      while (true) {
-        if (r + 2 <= h) s.pull(r + 2, c);
-        s.publish(r + 1, b, ring);
-        __syncthreads();
-        s.finish(r, a, ring);
-        if (++r >= h) break;
-        if (r + 2 <= h) s.pull(r + 2, a);
-        s.publish(r + 1, c, ring);
-        __syncthreads();
-        s.finish(r, b, ring);
-        if (++r >= h) break;
-        if (r + 2 <= h) s.pull(r + 2, b);
-        s.publish(r + 1, a, ring);
-        __syncthreads();
-        s.finish(r, c, ring);
-        if (++r >= h) break;
-      }
-    }
+      St s;
+      s.setup(dp, ti, sub);
+      march<St, PF>(s, ring);
     }
     __syncthreads();  // the next item reuses the ring (and next_item)
     if (grab) {
@@ -267,6 +351,37 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
     } else {
       it += gridDim.x;
     }
+  }
+}
+
+template <int NV>
+__device__ __forceinline__ void block_reduce(double (&v)[NV], const int (&op)[NV]);
+
+// A step that also records the diagnostics of the state it advances: one
+// partial record (kPartialStride doubles, the layout of the separate
+// diagnostics pass) per item, folded afterwards in item order.
+constexpr int kDiagThreads = 256;
+template <class S>
+__global__ __launch_bounds__(kDiagThreads) void k_step_diag(const InstDesc* __restrict__ descs,
+                                                            const TileItem* __restrict__ items,
+                                                            const int* __restrict__ nitems_p,
+                                                            int sub, double* __restrict__ partials) {
+  using St = Strip<S, kDiagThreads, 1, true>;
+  __shared__ float ring[4][St::SW + 2];
+  __shared__ double rring[4][St::SW + 2];
+  const int nitems = *nitems_p;
+  const int op[10] = {0, 0, 0, 0, 0, 1, 0, 0, 1, 2};
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
+    const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
+    St s;
+    s.setup(dp, ti, sub);
+    s.diag_zero();
+    march<St, 2>(s, ring, rring);
+    block_reduce<10>(s.acc, op);
+    if (threadIdx.x == 0)
+      for (int q = 0; q < 10; ++q) partials[(size_t)it * kPartialStride + q] = s.acc[q];
+    __syncthreads();  // the next item reuses the rings
   }
 }
 
@@ -1156,6 +1271,20 @@ hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, floa
   hipLaunchKernelGGL(k_diag_grad, dim3(g), dim3(kRedThreads), 0, st, (const double*)rho64, nx, ny,
                      partials);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, g,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_diag(int storage, const InstDesc* descs, const TileItem* items,
+                            const int* nitems, int grid, int sub, double* partials,
+                            double* out, hipStream_t st) {
+  if (storage == 0)
+    hipLaunchKernelGGL(k_step_diag<StoreF32>, dim3(grid), dim3(kDiagThreads), 0, st, descs, items,
+                       nitems, sub, partials);
+  else
+    hipLaunchKernelGGL(k_step_diag<StoreF16S>, dim3(grid), dim3(kDiagThreads), 0, st, descs, items,
+                       nitems, sub, partials);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, grid,
                      out);
   return hipGetLastError();
 }

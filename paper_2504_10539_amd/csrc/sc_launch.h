@@ -58,6 +58,15 @@ hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs&
 // Writes {mass, mom_x, mom_y, bad, n_above, Gmax, sum_grad, sum_grad2, rho_max, rho_min} to out.
 hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, float rho0,
                               double* rho64, double* partials, double* out, hipStream_t st);
+// One step that also records the diagnostics of the state it advances (the
+// ten values of launch_diagnostics, to out).  Strip tile of kSeriesThreads
+// threads x 1 cell, 2 rows in flight; `grid` = number of items (one partial
+// record of kPartialStride doubles each).
+constexpr int kSeriesThreads = 256;
+constexpr int kSeriesChunk = 256;  // records kept on the device between copies
+hipError_t launch_step_diag(int storage, const InstDesc* descs, const TileItem* items,
+                            const int* nitems, int grid, int sub, double* partials,
+                            double* out, hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 
 }  // namespace sclbm

@@ -69,6 +69,15 @@ WorkLayout work_layout(int nx, int ny) {
   o += (size_t)kMaxPartials * kPartialStride * sizeof(double);
   w.result = o;
   o += 256;
+  w.series_items = ((nx + kSeriesThreads - 1) / kSeriesThreads) * ((ny + kMinRows - 1) / kMinRows);
+  w.s_nitems = o;
+  o += 256;
+  w.s_items = o;
+  o = align_up(o + (size_t)w.series_items * sizeof(TileItem), 256);
+  w.s_partials = o;
+  o = align_up(o + (size_t)w.series_items * kPartialStride * sizeof(double), 256);
+  w.s_records = o;
+  o += (size_t)kSeriesChunk * 16 * sizeof(double);
   w.total = o;
   return w;
 }
@@ -256,8 +265,15 @@ lbm_status lbm_ctx::diagnostics(lbm_metrics* out) {
                                reinterpret_cast<double*>(idle), d_partials, d_result, stream));
   SCLBM_HIP(hipMemcpyAsync(h_result, d_result, 10 * sizeof(double), hipMemcpyDeviceToHost, stream));
   SCLBM_HIP(hipStreamSynchronize(stream));
+  *out = metrics_from_raw(h_result, steps);
+  return LBM_OK;
+}
+
+// Metrics from the ten raw values {mass, mom_x, mom_y, bad cells, cells above
+// the threshold, G_max, sum |grad rho|, sum |grad rho|^2, rho_max, rho_min}:
+// Eqs. (9)-(13) with V_total = nx * ny cells.
+lbm_metrics lbm_ctx::metrics_from_raw(const double* r, int64_t step) const {
   const double ncell = (double)p.nx * (double)p.ny;
-  const double* r = h_result;
   lbm_metrics m{};
   m.mass = r[0];
   m.mom_x = r[1];
@@ -272,8 +288,60 @@ lbm_status lbm_ctx::diagnostics(lbm_metrics* out) {
   m.W = r[4] / ncell;
   m.drho = r[8] - r[9];
   m.W_eff = r[5] > 0.0 ? r[6] / (r[5] * ncell) : 0.0;
-  m.step = steps;
-  *out = m;
+  m.step = step;
+  return m;
+}
+
+lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int32_t* count) {
+  if (series_nitems == 0) {
+    // strip tile of kSeriesThreads x 1 cell, 2 rows in flight, 8-row bands
+    const int k = find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + 0;
+    std::vector<TileItem> items;
+    make_items(p.nx, p.ny, k, 0, items);
+    items = xcd_order(items);
+    if ((int)items.size() > lay.series_items) return fail(LBM_EINVAL, "series tile table overflow");
+    const int ni = (int)items.size();
+    SCLBM_HIP(hipMemcpyAsync(d_sitems, items.data(), items.size() * sizeof(TileItem),
+                             hipMemcpyHostToDevice, stream));
+    SCLBM_HIP(hipMemcpyAsync(d_snitems, &ni, sizeof(int), hipMemcpyHostToDevice, stream));
+    SCLBM_HIP(hipStreamSynchronize(stream));
+    series_nitems = ni;
+  }
+  if (!h_series)
+    SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_series),
+                            (size_t)kSeriesChunk * 16 * sizeof(double), hipHostMallocDefault));
+  const int v = tile_variant(tile);
+  int32_t done = 0, pending = 0;
+  int64_t first_step = steps;
+  auto flush = [&]() -> lbm_status {
+    if (pending == 0) return LBM_OK;
+    SCLBM_HIP(hipMemcpyAsync(h_series, d_srecords, (size_t)pending * 16 * sizeof(double),
+                             hipMemcpyDeviceToHost, stream));
+    SCLBM_HIP(hipStreamSynchronize(stream));
+    for (int32_t q = 0; q < pending; ++q)
+      out[done + q] = metrics_from_raw(h_series + (size_t)q * 16, first_step + (int64_t)q * every);
+    done += pending;
+    first_step += (int64_t)pending * every;
+    pending = 0;
+    return LBM_OK;
+  };
+  for (int64_t j = 0; j < n; ++j) {
+    if (j % every == 0) {
+      SCLBM_HIP(launch_step_diag(p.storage, d_desc, d_sitems, d_snitems, series_nitems, parity,
+                                 d_spartials, d_srecords + (size_t)pending * 16, stream));
+      if (++pending == kSeriesChunk) {
+        const lbm_status s = flush();
+        if (s != LBM_OK) return s;
+      }
+    } else {
+      SCLBM_HIP(launch_step(p.storage, v, d_desc, d_items, d_nitems, nitems, parity, stream));
+    }
+    parity ^= 1;
+    steps += 1;
+  }
+  const lbm_status s = flush();
+  if (s != LBM_OK) return s;
+  *count = done;
   return LBM_OK;
 }
 
@@ -551,6 +619,10 @@ lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_by
   c->d_items = reinterpret_cast<TileItem*>(w + lay.items);
   c->d_partials = reinterpret_cast<double*>(w + lay.partials);
   c->d_result = reinterpret_cast<double*>(w + lay.result);
+  c->d_snitems = reinterpret_cast<int*>(w + lay.s_nitems);
+  c->d_sitems = reinterpret_cast<TileItem*>(w + lay.s_items);
+  c->d_spartials = reinterpret_cast<double*>(w + lay.s_partials);
+  c->d_srecords = reinterpret_cast<double*>(w + lay.s_records);
   c->arch = device_arch();
   const InstDesc d = c->host_desc();
   hipError_t e = hipMemcpyAsync(c->d_desc, &d, sizeof d, hipMemcpyHostToDevice, c->stream);
@@ -575,6 +647,7 @@ lbm_status lbm_destroy(lbm_ctx* c) {
   if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
   const hipError_t e = hipStreamSynchronize(c->stream);
   if (c->h_result) (void)hipHostFree(c->h_result);
+  if (c->h_series) (void)hipHostFree(c->h_series);
   delete c;
   return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
 }
@@ -639,6 +712,18 @@ lbm_status lbm_step_n(lbm_ctx* c, int64_t n) {
     c->steps += 1;
   }
   return LBM_OK;
+}
+
+lbm_status lbm_step_series(lbm_ctx* c, int64_t n, int32_t every, lbm_metrics* out,
+                           int32_t capacity, int32_t* count) {
+  if (!c || !count) return fail(LBM_EINVAL, "ctx or count is NULL");
+  *count = 0;
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  if (n < 0 || every < 1) return fail(LBM_EINVAL, "need n >= 0 and every >= 1");
+  const int64_t need = (n + every - 1) / every;
+  if (need > capacity || (need > 0 && !out))
+    return fail(LBM_EINVAL, "out holds fewer than ceil(n / every) records");
+  return c->step_series(n, every, out, count);
 }
 
 lbm_status lbm_moments(lbm_ctx* c, float* rho, float* ux, float* uy) {

@@ -56,8 +56,11 @@ std::vector<TileItem> xcd_order(const std::vector<TileItem>& items);
 
 // Workspace layout of a single run.
 struct WorkLayout {
-  size_t desc, nitems, items, partials, result, total;
-  int max_items;
+  size_t desc, nitems, items, partials, result;
+  // metric series: its own tile table, one partial record per item, records
+  size_t s_nitems, s_items, s_partials, s_records;
+  size_t total;
+  int max_items, series_items;
 };
 WorkLayout work_layout(int nx, int ny);
 
@@ -136,10 +139,18 @@ struct lbm_ctx {
   double* d_partials = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;  // pinned
+  int* d_snitems = nullptr;     // metric-series tile table (built on first use)
+  sclbm::TileItem* d_sitems = nullptr;
+  double* d_spartials = nullptr;
+  double* d_srecords = nullptr;
+  double* h_series = nullptr;  // pinned, kSeriesChunk records
+  int series_nitems = 0;
   lbm_batch* batch = nullptr;  // non-null while driven by a batch
   std::string arch;
 
   sclbm::InstDesc host_desc() const;
   lbm_status upload_tile(int k);
   lbm_status diagnostics(lbm_metrics* out);
+  lbm_status step_series(int64_t n, int32_t every, lbm_metrics* out, int32_t* count);
+  lbm_metrics metrics_from_raw(const double* r, int64_t step) const;
 };

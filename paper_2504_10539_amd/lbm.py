@@ -109,6 +109,7 @@ _PROTOS = {
     "lbm_destroy": (_i32, [_vp]),
     "lbm_init_droplets": (_i32, [_vp, _P(ctypes.c_double), _i32, _P(lbm_init)]),
     "lbm_step_n": (_i32, [_vp, _i64]),
+    "lbm_step_series": (_i32, [_vp, _i64, _i32, _P(lbm_metrics), _i32, _P(_i32)]),
     "lbm_moments": (_i32, [_vp, _vp, _vp, _vp]),
     "lbm_interface_metrics": (_i32, [_vp, _P(lbm_metrics)]),
     "lbm_get_state": (_i32, [_vp, _vp]),
@@ -306,6 +307,15 @@ class Simulation:
         m = lbm_metrics()
         _check(LIB.lbm_interface_metrics(self.handle, ctypes.byref(m)), "lbm_interface_metrics")
         return m.as_dict()
+
+    def step_series(self, n: int, every: int) -> list[dict]:
+        """n steps; metrics of every `every`-th state on the way (ceil(n / every) records)."""
+        cap = max(1, -(-int(n) // max(1, int(every))))
+        out = (lbm_metrics * cap)()
+        cnt = _i32()
+        _check(LIB.lbm_step_series(self.handle, int(n), int(every), out, cap, ctypes.byref(cnt)),
+               "lbm_step_series")
+        return [out[k].as_dict() for k in range(cnt.value)]
 
     def get_state(self):
         torch = _torch()

@@ -93,6 +93,8 @@ def test_buffer_sizes_and_validation(lbm):
     assert lbm.LIB.lbm_create(ctypes.byref(p), 256, 512, 10, 768, work.value, None,
                               ctypes.byref(h)) == lbm.LBM_ENOMEM
     assert lbm.LIB.lbm_step_n(None, 1) == lbm.LBM_EINVAL
+    cnt = ctypes.c_int32(7)
+    assert lbm.LIB.lbm_step_series(None, 1, 1, None, 0, ctypes.byref(cnt)) == lbm.LBM_EINVAL
     assert lbm.LIB.lbm_stream_copy(None, None, 16, None) == lbm.LBM_EINVAL
 
 

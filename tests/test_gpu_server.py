@@ -2,7 +2,9 @@
 
 Requests of uneven sizes and both storage types are admitted while others run
 (continuous batching); every final state must equal, bitwise, the same
-request run alone on a server and run by the plain single-run path.  A
+request run alone on a server, and the plain single-run path's result (a
+different kernel variant) in every finite value and in which cells are not
+finite.  A
 request with unstable parameters is flagged without disturbing the others.
 """
 import numpy as np
@@ -50,6 +52,15 @@ def _bits(a):
     return np.ascontiguousarray(a, dtype=np.float32).view(np.uint32)
 
 
+def _same_across_variants(a, b):
+    """Equality of results from different kernel variants: finite values
+    bitwise, non-finite values in the same cells.  The sign and payload of a
+    NaN depend on the operand order of the instruction that propagates it,
+    which the variants do not fix, so NaN bits are not compared."""
+    fa, fb = np.isfinite(a), np.isfinite(b)
+    return np.array_equal(fa, fb) and np.array_equal(_bits(a[fa]), _bits(b[fb]))
+
+
 def test_results_equal_alone_and_in_the_mix():
     L = lbm()
     srv = L.Server(2 << 30, steps_per_tick=16, max_slots=8)
@@ -72,7 +83,7 @@ def test_results_equal_alone_and_in_the_mix():
         assert alone.poll(t)[0] == codes[k]
         assert np.array_equal(_bits(f.cpu().numpy()), _bits(mixed[k])), k
         alone.close()
-        assert np.array_equal(_bits(_solo_plain(k, r)), _bits(mixed[k])), k
+        assert _same_across_variants(_solo_plain(k, r), mixed[k]), k
 
 
 def test_fifo_policy_matches_continuous():
