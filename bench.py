@@ -17,8 +17,8 @@ resident; `roofline` prices the step kernel (the dominant kernel) at 72
 algorithmic bytes per lattice update against the 8 TB/s HBM peak, with the
 kernel's average launch time measured by HIP events on its stream over the
 timed region.  Extra objects report the FP16-shifted storage, a 1024^2
-single-droplet run, the batched parameter sweep, the serving loop and the FP64
-oracle's CPU rate.
+single-droplet run, the paper's own droplet protocol (Tables I-II layout), the
+batched parameter sweep, the serving loop and the FP64 oracle's CPU rate.
 """
 from __future__ import annotations
 
@@ -173,6 +173,20 @@ def run_single_droplet(args, torch, lbm, inputs):
         f"{res['mlups']:.0f} MLUPS whole run")
     sim.close()
     torch.cuda.empty_cache()
+    return res
+
+
+def run_paper_preset(args, torch, lbm):
+    """The paper's pure-LBM protocol (R = nx/6, G -5.5, tau 1.0; 500 steps, then five
+    segments) on a 256^2 grid, with the FP16-shifted fork from the common state."""
+    from paper_2504_10539_amd import preset
+    t0 = time.perf_counter()
+    r = preset.run(nx=256, segment=500, every=50, fork_storage=lbm.LBM_F16_SHIFTED)
+    torch.cuda.synchronize()
+    res = {"workload": "paper_droplet_256", "steps": 500 + 5 * 500, "wall_s": time.perf_counter() - t0,
+           "table_I": r["table_I"], "table_II": r["table_II"],
+           "fp16_fork": {"table_I": r["fork"]["table_I"], "table_II": r["fork"]["table_II"]}}
+    log(f"[paper preset 256^2] table I {res['table_I']}, table II {res['table_II']}")
     return res
 
 
@@ -369,6 +383,7 @@ def main():
         line["f16_shifted"] = f16
     if not args.no_extras:
         line["single_droplet_1024"] = run_single_droplet(args, torch, lbm, inputs)
+        line["paper_preset"] = run_paper_preset(args, torch, lbm)
         line["sweep_512x256"] = run_sweep(args, torch, lbm, inputs)
         line["serving"] = run_serving(args, torch, lbm, inputs)
         if not args.no_cpu:
