@@ -19,12 +19,14 @@ struct StepVariant {
 constexpr int kNumVariants = 20;
 constexpr int kPairColumns = 124;
 constexpr int kPairMinNx = 128;
-// Band heights a tile shape may use; tile shape k = variant * kNumRows + row index.
-constexpr int kRowChoices[] = {8, 16, 32, 64, 128};
-constexpr int kNumRows = 5;
+// Band heights a tile shape may use; tile shape k = variant * kNumRows + row
+// index.  The short bands (2, 4 rows) give grids too small to fill the GPU
+// with long bands enough workgroups in flight.
+constexpr int kRowChoices[] = {8, 16, 32, 64, 128, 2, 4};
+constexpr int kNumRows = 7;
 constexpr int kNumTiles = kNumVariants * kNumRows;
 constexpr int kMinStripWidth = 64;
-constexpr int kMinRows = 8;
+constexpr int kMinRows = 2;
 
 // Longest graph of batched steps (time steps per replay).
 constexpr int kMaxGraphSteps = 4096;

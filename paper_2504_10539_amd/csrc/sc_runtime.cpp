@@ -69,7 +69,9 @@ WorkLayout work_layout(int nx, int ny) {
   o += (size_t)kMaxPartials * kPartialStride * sizeof(double);
   w.result = o;
   o += 256;
-  w.series_items = ((nx + kSeriesThreads - 1) / kSeriesThreads) * ((ny + kMinRows - 1) / kMinRows);
+  // the series tile: kSeriesThreads-wide strips, row index 0 (8-row bands)
+  w.series_items = ((nx + kSeriesThreads - 1) / kSeriesThreads) *
+                   ((ny + kRowChoices[0] - 1) / kRowChoices[0]);
   w.s_nitems = o;
   o += 256;
   w.s_items = o;

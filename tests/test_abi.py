@@ -101,7 +101,7 @@ def test_buffer_sizes_and_validation(lbm):
 def test_tile_table(lbm):
     tiles = lbm.tiles()
     assert len(tiles) == lbm.LIB.lbm_tile_count()
-    assert all(t["width"] >= 64 and t["rows"] >= 8 for t in tiles)
+    assert all(t["width"] >= 64 and t["rows"] >= 2 for t in tiles)
     assert len({(t["width"], t["rows"], t["threads"], t["prefetch"]) for t in tiles}) == len(tiles)
     w = ctypes.c_int32()
     assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None, None,
