@@ -259,6 +259,14 @@ def run_serving(args, torch, lbm, inputs):
             while srv.clock() - t0 < r.arrival:
                 time.sleep(min(0.001, max(0.0, r.arrival - (srv.clock() - t0))))
             tickets.append(srv.submit(r.n, r.n, r.G, r.tau, r.steps, r.drops, seed=r.seed))
+            if len(tickets) % 250 == 0:
+                log(f"[serving {name}] {len(tickets)} submitted, {srv.stats()['completed']} done")
+        last = time.perf_counter()
+        while srv.stats()["completed"] < len(tickets):
+            time.sleep(0.05)
+            if time.perf_counter() - last > 15.0:
+                last = time.perf_counter()
+                log(f"[serving {name}] {srv.stats()['completed']} of {len(tickets)} done")
         srv.drain()
         lat, done, unstable = [], [], 0
         for t in tickets:
@@ -317,7 +325,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--c2-steps", type=int, default=10000)
-    ap.add_argument("--only", choices=["single_droplet_1024"], default=None,
+    ap.add_argument("--only", choices=["single_droplet_1024", "serving"], default=None,
                     help="run one extra workload alone and print its result (for profiling)")
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--sweep-instances", type=int, default=512)
@@ -343,6 +351,9 @@ def main():
 
     if args.only == "single_droplet_1024":
         print(json.dumps(run_single_droplet(args, torch, lbm, inputs)), flush=True)
+        return
+    if args.only == "serving":
+        print(json.dumps(run_serving(args, torch, lbm, inputs)), flush=True)
         return
     log(f"device {torch.cuda.get_device_name(0)}; workload {args.n}^2, {args.drops} droplets, "
         f"G {args.G}, tau {args.tau}, {args.lbm_steps} LBM steps per job")
