@@ -80,7 +80,9 @@ typedef struct lbm_params {
  * centre; eta = noise_amp (2u - 1), u in [0, 1) the top 53 bits of the
  * (gy * period_x + gx)-th output of SplitMix64 seeded with `seed`
  * (gx, gy the cell's frame coordinates).  period 0 means the grid itself and
- * requires origin 0.  The fluid starts at rest: f_i = w_i rho. */
+ * requires origin 0; the grid must lie inside the frame (origin + nx <=
+ * period_x, origin + ny <= period_y).  The fluid starts at rest:
+ * f_i = w_i rho. */
 typedef struct lbm_init {
   double rho_l, rho_g;   /* liquid and gas densities */
   double width;          /* tanh width (> 0) */

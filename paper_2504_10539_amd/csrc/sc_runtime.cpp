@@ -681,6 +681,8 @@ lbm_status lbm_init_droplets(lbm_ctx* c, const double* drops, int32_t n, const l
     return fail(LBM_EINVAL, "period and origin must be >= 0");
   if ((ip->period_x == 0 && ip->origin_x != 0) || (ip->period_y == 0 && ip->origin_y != 0))
     return fail(LBM_EINVAL, "origin requires an explicit period");
+  if (a.origin_x + c->p.nx > a.period_x || a.origin_y + c->p.ny > a.period_y)
+    return fail(LBM_EINVAL, "the grid must lie inside the frame: origin + n <= period");
   // Scratch in the second buffer: rho (FP64) then the droplet list.
   const size_t ncell = (size_t)c->p.nx * c->p.ny;
   const size_t drop_off = align_up(ncell * sizeof(double), 256);
