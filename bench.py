@@ -176,6 +176,38 @@ def run_single_droplet(args, torch, lbm, inputs):
     return res
 
 
+def run_series_cost(args, torch, lbm, inputs):
+    """Cost of the fused metric time series on the bench workload: 500 FP32 steps with
+    the interface metrics of every 10th state, against 500 plain steps and against
+    50 separate diagnostics passes."""
+    N = args.n
+    drops = inputs.many_droplets(N, args.drops, 8, 48, seed=3)
+    sim = lbm.Simulation(N, N, args.G, args.tau, lbm.LBM_F32)
+    sim.init_droplets(drops, seed=3)
+    sim.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(500)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    recs = sim.step_series(500, 10)
+    series = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(50):
+        sim.step(10)
+        sim.metrics()
+    separate = time.perf_counter() - t0
+    sim.close()
+    torch.cuda.empty_cache()
+    res = {"workload": f"many_droplets_{N}", "steps": 500, "every": 10, "records": len(recs),
+           "plain_ms": plain * 1e3, "series_ms": series * 1e3, "separate_passes_ms": separate * 1e3,
+           "series_overhead": series / plain - 1.0, "separate_overhead": separate / plain - 1.0}
+    log(f"[metric series] plain {plain*1e3:.1f} ms, fused series {series*1e3:.1f} ms, "
+        f"separate passes {separate*1e3:.1f} ms")
+    return res
+
+
 def run_paper_preset(args, torch, lbm):
     """The paper's pure-LBM protocol (R = nx/6, G -5.5, tau 1.0; 500 steps, then five
     segments) on a 256^2 grid, with the FP16-shifted fork from the common state."""
@@ -395,6 +427,7 @@ def main():
     if not args.no_extras:
         line["single_droplet_1024"] = run_single_droplet(args, torch, lbm, inputs)
         line["paper_preset"] = run_paper_preset(args, torch, lbm)
+        line["metric_series"] = run_series_cost(args, torch, lbm, inputs)
         line["sweep_512x256"] = run_sweep(args, torch, lbm, inputs)
         line["serving"] = run_serving(args, torch, lbm, inputs)
         if not args.no_cpu:
