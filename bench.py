@@ -36,6 +36,7 @@ sys.path.insert(0, HERE)
 HBM_PEAK_GBS = 8000.0
 BYTES_F32 = 72   # 9 populations read + 9 written, 4 bytes each
 BYTES_F16 = 36
+BYTES_F16_CELL = 40  # 18 B read + 18 B written, plus the 2-byte reference density each way
 
 
 def log(msg: str):
@@ -61,8 +62,8 @@ def traffic_from_profiles(lbm, kernel_hash: str, storage: str, n: int, tile: int
     except (OSError, ValueError):
         return None
     t = lbm.tiles()[tile]
-    key = (storage, n, kernel_name(lbm, tile, lbm.LBM_F32 if storage == "f32" else lbm.LBM_F16_SHIFTED),
-           t["width"], t["rows"])
+    code = {"f32": lbm.LBM_F32, "f16_shifted": lbm.LBM_F16_SHIFTED, "f16_cell": lbm.LBM_F16_CELL}[storage]
+    key = (storage, n, kernel_name(lbm, tile, code), t["width"], t["rows"])
     for e in d.get("entries", []):
         if (e.get("storage"), e.get("n"), e.get("kernel"), e.get("width"), e.get("rows")) == key:
             return e.get("bytes_per_launch") if e.get("kernel_hash") == kernel_hash else None
@@ -72,7 +73,7 @@ def traffic_from_profiles(lbm, kernel_hash: str, storage: str, n: int, tile: int
 def kernel_name(lbm, tile: int, storage: int) -> str:
     """Name of the step kernel instance that tile shape `tile` launches."""
     t = lbm.tiles()[tile]
-    st = "StoreF32" if storage == lbm.LBM_F32 else "StoreF16S"
+    st = {lbm.LBM_F32: "StoreF32", lbm.LBM_F16_SHIFTED: "StoreF16S", lbm.LBM_F16_CELL: "StoreF16C"}[storage]
     if t["paired"]:
         return f"k_step_pair<{st}, {t['threads'] // 64}, {t['prefetch']}>"
     return f"k_step<{st}, {t['threads']}, {t['cells']}, {t['prefetch']}>"
@@ -83,8 +84,9 @@ def run_main(args, torch, lbm, inputs):
     drops = inputs.many_droplets(N, args.drops, 8, 48, seed=3)
     stream = torch.cuda.current_stream()
     out = {}
-    for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted")):
-        if storage == lbm.LBM_F16_SHIFTED and args.no_fp16:
+    for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted"),
+                          (lbm.LBM_F16_CELL, "f16_cell")):
+        if storage != lbm.LBM_F32 and args.no_fp16:
             continue
         rho0 = 1.0 if storage == lbm.LBM_F16_SHIFTED else 0.0
         sim = lbm.Simulation(N, N, args.G, args.tau, storage, rho0)
@@ -123,7 +125,8 @@ def run_main(args, torch, lbm, inputs):
         wall = time.perf_counter() - t0
         lu = float(N) * N * args.lbm_steps * args.steps
         launch_ms = sum(step_ms) / (args.lbm_steps * args.steps)
-        bpu = BYTES_F32 if storage == lbm.LBM_F32 else BYTES_F16
+        bpu = {lbm.LBM_F32: BYTES_F32, lbm.LBM_F16_SHIFTED: BYTES_F16,
+               lbm.LBM_F16_CELL: BYTES_F16_CELL}[storage]
         achieved = bpu * N * N / (launch_ms * 1e-3) / 1e9
         out[name] = {
             "mlups": lu / wall / 1e6,
@@ -419,11 +422,11 @@ def main():
                      "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
         "f32": f32,
     }
-    if "f16_shifted" in main_res:
-        f16 = main_res["f16_shifted"]
-        f16 = dict(f16, roofline_frac=round(f16["achieved_gbs"] / HBM_PEAK_GBS, 4),
-                   traffic=traffic_from_profiles(lbm, khash, "f16_shifted", args.n, f16["tile"]))
-        line["f16_shifted"] = f16
+    for key in ("f16_shifted", "f16_cell"):
+        if key in main_res:
+            r = main_res[key]
+            line[key] = dict(r, roofline_frac=round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),
+                             traffic=traffic_from_profiles(lbm, khash, key, args.n, r["tile"]))
     if not args.no_extras:
         line["single_droplet_1024"] = run_single_droplet(args, torch, lbm, inputs)
         line["paper_preset"] = run_paper_preset(args, torch, lbm)

@@ -58,6 +58,13 @@ typedef int32_t lbm_status;
 #define LBM_F16_SHIFTED 1  /* FP16 h_i = f_i - w_i rho0 (round to nearest even),
                               read back as float(h_i) + w_i rho0; 18 bytes per
                               cell per buffer; arithmetic stays FP32 */
+#define LBM_F16_CELL 2     /* FP16 shifted per cell: the nine values a cell x
+                              stores hold A_i(x) - w_i rhohat(x) (the FP32
+                              difference rounded once to nearest even), with
+                              rhohat(x) = half(rho) of that cell stored in a
+                              tenth FP16 plane; read back as rhohat w_i + h_i
+                              rounded once.  20 bytes per cell per buffer, 40
+                              bytes moved per lattice update */
 
 typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;
@@ -68,8 +75,8 @@ typedef struct lbm_params {
   int32_t nx, ny;   /* grid size, periodic in x and y; 1 <= nx, ny <= 65536 */
   double G;         /* interaction strength (negative for attraction), finite */
   double tau;       /* BGK relaxation time, tau > 0.5 */
-  int32_t storage;  /* LBM_F32 or LBM_F16_SHIFTED */
-  double rho0;      /* FP16 shift density (finite, >= 0); ignored for LBM_F32 */
+  int32_t storage;  /* LBM_F32, LBM_F16_SHIFTED or LBM_F16_CELL */
+  double rho0;      /* LBM_F16_SHIFTED's shift density (finite, >= 0); ignored otherwise */
 } lbm_params;
 
 /* Droplet initial condition (Sec. III-A).  For each cell (x, y):
@@ -113,7 +120,8 @@ typedef struct lbm_metrics {
 /* ------------------------------------------------------------ single run */
 
 /* Sizes the caller must allocate for one run: `pop_bytes` for EACH of the two
- * population buffers (9 * nx * ny * 4 for LBM_F32, * 2 for LBM_F16_SHIFTED),
+ * population buffers (9 * nx * ny * 4 for LBM_F32, * 2 for LBM_F16_SHIFTED,
+ * 10 * nx * ny * 2 for LBM_F16_CELL),
  * and `work_bytes` of device workspace (tile tables and reduction partials).
  * Either output pointer may be NULL.  LBM_EINVAL for invalid parameters. */
 lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes);

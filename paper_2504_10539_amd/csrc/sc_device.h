@@ -69,6 +69,13 @@ __host__ __device__ __forceinline__ uint64_t pop_index(int i, int x, int y, int 
   return row_index(i, y, nx, ny) + (uint64_t)x;
 }
 
+// Per-cell-shift storage keeps one more plane after the nine populations:
+// rhohat(x), the reference density of the cell that wrote the nine values
+// stored at x.  Row y of that plane starts at element 9 nx ny + y nx.
+__host__ __device__ __forceinline__ uint64_t rhat_row(int y, int nx, int ny) {
+  return 9ull * (uint64_t)nx * (uint64_t)ny + (uint64_t)y * (uint64_t)nx;
+}
+
 // ------------------------------------------------------------------ storage
 
 // FP32 populations.  Stores stream past the caches (the buffer written is
@@ -77,6 +84,7 @@ struct StoreF32 {
   using T = float;
   static constexpr int kBytes = 4;
   static constexpr bool kStream = true;
+  static constexpr bool kCellShift = false;
   template <class P>
   __device__ static __forceinline__ float load(P p, float /*shift*/) { return *p; }
   __device__ static __forceinline__ T pack(float v, float /*shift*/) { return v; }
@@ -87,6 +95,7 @@ struct StoreF16S {
   using T = _Float16;
   static constexpr int kBytes = 2;
   static constexpr bool kStream = false;
+  static constexpr bool kCellShift = false;
   template <class P>
   __device__ static __forceinline__ float load(P p, float shift) {
     return static_cast<float>(*p) + shift;
@@ -94,6 +103,25 @@ struct StoreF16S {
   __device__ static __forceinline__ T pack(float v, float shift) {
     return static_cast<T>(v - shift);  // v_cvt_f16_f32: round to nearest even
   }
+};
+
+// FP16 populations shifted per cell: the nine values a cell stores hold
+// f_i - w_i rhohat, where rhohat = half(rho) of that (writing) cell and is
+// stored beside them (rhat_row).  Read back as rhohat * w_i + h, rounded
+// once.  Only the non-equilibrium and velocity parts of f_i are left to round
+// to half precision, in either phase.
+struct StoreF16C {
+  using T = _Float16;
+  static constexpr int kBytes = 2;
+  static constexpr bool kStream = false;
+  static constexpr bool kCellShift = true;
+  __device__ static __forceinline__ float decode(T h, T rh, float w) {
+    return __builtin_fmaf(static_cast<float>(rh), w, static_cast<float>(h));
+  }
+  __device__ static __forceinline__ T encode(float v, T rh, float w) {
+    return static_cast<T>(__builtin_fmaf(-w, static_cast<float>(rh), v));
+  }
+  __device__ static __forceinline__ T ref(float rho) { return static_cast<T>(rho); }
 };
 
 // Pointer into global memory (address space 1): loads and stores through it

@@ -64,6 +64,13 @@ struct Strip {
   __device__ __forceinline__ gptr<T> out_row(int i, int y) const {
     return as_global<T>(uniform(dst + row_index(i, y, nx, ny) * sizeof(T)));
   }
+  // Row y of the reference-density plane (per-cell-shift storage).
+  __device__ __forceinline__ gptr<const T> rhat_in(int y) const {
+    return as_global<const T>(uniform(src + rhat_row(y, nx, ny) * sizeof(T)));
+  }
+  __device__ __forceinline__ gptr<T> rhat_out(int y) const {
+    return as_global<T>(uniform(dst + rhat_row(y, nx, ny) * sizeof(T)));
+  }
 
   __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti,
                                         int sub) {
@@ -143,15 +150,30 @@ struct Strip {
       if (live[k]) {
         const uint32_t c = fresh((uint32_t)xc[k] * B), m = fresh((uint32_t)xm[k] * B),
                        p = fresh((uint32_t)xp[k] * B);
-        f[k][0] = S::load(at(p0, c), sh[0]);
-        f[k][1] = S::load(at(p1, m), sh[1]);
-        f[k][2] = S::load(at(p2, c), sh[2]);
-        f[k][3] = S::load(at(p3, p), sh[3]);
-        f[k][4] = S::load(at(p4, c), sh[4]);
-        f[k][5] = S::load(at(p5, m), sh[5]);
-        f[k][6] = S::load(at(p6, p), sh[6]);
-        f[k][7] = S::load(at(p7, p), sh[7]);
-        f[k][8] = S::load(at(p8, m), sh[8]);
+        if constexpr (S::kCellShift) {
+          // each value is decoded with the reference density of the cell it
+          // was read from (same row and column in the reference plane)
+          const gptr<const T> q0 = rhat_in(y), qm = rhat_in(ym), qp = rhat_in(yp);
+          f[k][0] = S::decode(*at(p0, c), *at(q0, c), kW0);
+          f[k][1] = S::decode(*at(p1, m), *at(q0, m), kW1);
+          f[k][2] = S::decode(*at(p2, c), *at(qm, c), kW1);
+          f[k][3] = S::decode(*at(p3, p), *at(q0, p), kW1);
+          f[k][4] = S::decode(*at(p4, c), *at(qp, c), kW1);
+          f[k][5] = S::decode(*at(p5, m), *at(qm, m), kW2);
+          f[k][6] = S::decode(*at(p6, p), *at(qm, p), kW2);
+          f[k][7] = S::decode(*at(p7, p), *at(qp, p), kW2);
+          f[k][8] = S::decode(*at(p8, m), *at(qp, m), kW2);
+        } else {
+          f[k][0] = S::load(at(p0, c), sh[0]);
+          f[k][1] = S::load(at(p1, m), sh[1]);
+          f[k][2] = S::load(at(p2, c), sh[2]);
+          f[k][3] = S::load(at(p3, p), sh[3]);
+          f[k][4] = S::load(at(p4, c), sh[4]);
+          f[k][5] = S::load(at(p5, m), sh[5]);
+          f[k][6] = S::load(at(p6, p), sh[6]);
+          f[k][7] = S::load(at(p7, p), sh[7]);
+          f[k][8] = S::load(at(p8, m), sh[8]);
+        }
       }
     }
   }
@@ -250,12 +272,20 @@ struct Strip {
                dn[c + 1], G, Fx, Fy);
       collide(f[k], f[k][9], Fx, Fy, tau, omega);
       const uint32_t xb = fresh((uint32_t)xc[k] * (uint32_t)sizeof(T));
+      if constexpr (S::kCellShift) {
+        const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+        const T rh = S::ref(f[k][9]);  // this cell's reference: half(rho)
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        if constexpr (S::kStream)
-          __builtin_nontemporal_store(S::pack(f[k][i], sh[i]), at(o[i], xb));
-        else
-          *at(o[i], xb) = S::pack(f[k][i], sh[i]);
+        for (int i = 0; i < 9; ++i) *at(o[i], xb) = S::encode(f[k][i], rh, ws[i]);
+        *at(rhat_out(y), xb) = rh;
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          if constexpr (S::kStream)
+            __builtin_nontemporal_store(S::pack(f[k][i], sh[i]), at(o[i], xb));
+          else
+            *at(o[i], xb) = S::pack(f[k][i], sh[i]);
+        }
       }
     }
   }
@@ -475,6 +505,30 @@ struct PairIO<StoreF16S> {
   }
 };
 
+// Per-cell-shift FP16: the reference density q and the stored value h are
+// two halves of two words; q * w + h in one mixed-precision FMA (single
+// rounding, exactly StoreF16C::decode).  _lo takes the low halves, _hi the
+// high halves.
+__device__ __forceinline__ float mix_lo(uint32_t q, float w, uint32_t h) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(q), "v"(w), "v"(h));
+  return r;
+}
+__device__ __forceinline__ float mix_hi(uint32_t q, float w, uint32_t h) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,1] op_sel_hi:[1,0,1]"
+      : "=v"(r) : "v"(q), "v"(w), "v"(h));
+  return r;
+}
+
+template <>
+struct PairIO<StoreF16C> {
+  using W = uint32_t;
+  __device__ static __forceinline__ W pack(_Float16 a, _Float16 b) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
+  }
+};
+
 // psi of one row around a lane's pair (left neighbour, the two cells, right
 // neighbour) and the densities of the two cells.
 struct PsiRow {
@@ -487,6 +541,9 @@ struct PairStrip {
   using T = typename S::T;
   using IO = PairIO<S>;
   using W = typename IO::W;
+  // words a lane loads per row: the nine populations, plus the reference
+  // density of rows y, y - 1, y + 1 for per-cell-shift storage
+  static constexpr int kWords = S::kCellShift ? 12 : 9;
 
   uint64_t src, dst;
   float sh[9];
@@ -514,6 +571,14 @@ struct PairStrip {
   }
   __device__ __forceinline__ gptr<W> out_pair(int i, int y, uint32_t o) const {
     const uint64_t row = uniform(dst + row_index(i, y, nx, ny) * sizeof(T));
+    return reinterpret_cast<gptr<W>>(as_global<char>(row) + o);
+  }
+  __device__ __forceinline__ gptr<const W> rhat_in_pair(int y, uint32_t o) const {
+    const uint64_t row = uniform(src + rhat_row(y, nx, ny) * sizeof(T));
+    return reinterpret_cast<gptr<const W>>(as_global<const char>(row) + o);
+  }
+  __device__ __forceinline__ gptr<W> rhat_out_pair(int y, uint32_t o) const {
+    const uint64_t row = uniform(dst + rhat_row(y, nx, ny) * sizeof(T));
     return reinterpret_cast<gptr<W>>(as_global<char>(row) + o);
   }
 
@@ -549,7 +614,7 @@ struct PairStrip {
   }
 
   // Raw stored pairs feeding row j: population i comes from row y - e_iy.
-  __device__ __forceinline__ void load(int j, W (&w)[9]) const {
+  __device__ __forceinline__ void load(int j, W (&w)[kWords]) const {
     const int y = row_of(j);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
     const uint32_t o = lane_offset();
@@ -562,14 +627,43 @@ struct PairStrip {
     w[6] = *in_pair(6, ym, o);
     w[7] = *in_pair(7, yp, o);
     w[8] = *in_pair(8, yp, o);
+    if constexpr (S::kCellShift) {
+      w[9] = *rhat_in_pair(y, o);
+      w[10] = *rhat_in_pair(ym, o);
+      w[11] = *rhat_in_pair(yp, o);
+    }
   }
 
   // Pre-collision populations of the pair's two cells and the row's psi.
   // Populations pulled from x - 1 (e_ix = +1: 1, 5, 8) take the previous
   // lane's upper cell for cell a; those pulled from x + 1 (e_ix = -1: 3, 6, 7)
   // take the next lane's lower cell for cell b.
-  __device__ __forceinline__ void expand(const W (&w)[9], float (&fa)[9], float (&fb)[9],
+  __device__ __forceinline__ void expand(const W (&w)[kWords], float (&fa)[9], float (&fb)[9],
                                          PsiRow& ps) const {
+    if constexpr (S::kCellShift) {
+      // each value with the reference density of the cell it was read from
+      const W qy = w[9], qm = w[10], qp = w[11];
+      const W pqy = lane_from_prev(qy), pqm = lane_from_prev(qm), pqp = lane_from_prev(qp);
+      const W nqy = lane_from_next(qy), nqm = lane_from_next(qm), nqp = lane_from_next(qp);
+      fa[0] = mix_lo(qy, kW0, w[0]);
+      fb[0] = mix_hi(qy, kW0, w[0]);
+      fa[2] = mix_lo(qm, kW1, w[2]);
+      fb[2] = mix_hi(qm, kW1, w[2]);
+      fa[4] = mix_lo(qp, kW1, w[4]);
+      fb[4] = mix_hi(qp, kW1, w[4]);
+      fa[1] = mix_hi(pqy, kW1, lane_from_prev(w[1]));
+      fb[1] = mix_lo(qy, kW1, w[1]);
+      fa[5] = mix_hi(pqm, kW2, lane_from_prev(w[5]));
+      fb[5] = mix_lo(qm, kW2, w[5]);
+      fa[8] = mix_hi(pqp, kW2, lane_from_prev(w[8]));
+      fb[8] = mix_lo(qp, kW2, w[8]);
+      fa[3] = mix_hi(qy, kW1, w[3]);
+      fb[3] = mix_lo(nqy, kW1, lane_from_next(w[3]));
+      fa[6] = mix_hi(qm, kW2, w[6]);
+      fb[6] = mix_lo(nqm, kW2, lane_from_next(w[6]));
+      fa[7] = mix_hi(qp, kW2, w[7]);
+      fb[7] = mix_lo(nqp, kW2, lane_from_next(w[7]));
+    } else {
     fa[0] = IO::lo(w[0], sh[0]);
     fb[0] = IO::hi(w[0], sh[0]);
     fa[2] = IO::lo(w[2], sh[2]);
@@ -588,6 +682,7 @@ struct PairStrip {
     fb[6] = IO::lo_of_next(w[6], sh[6]);
     fa[7] = IO::hi(w[7], sh[7]);
     fb[7] = IO::lo_of_next(w[7], sh[7]);
+    }
     ps.rho_a = density(fa);
     ps.rho_b = density(fb);
     ps.a = psi_of(ps.rho_a);
@@ -610,13 +705,22 @@ struct PairStrip {
     if (out_ok) {
       const int y = row_of(r);
       const uint32_t o = lane_offset();
+      if constexpr (S::kCellShift) {
+        const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+        const T ra = S::ref(md.rho_a), rb = S::ref(md.rho_b);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) {
-        const W v = IO::make(fa[i], fb[i], sh[i], sh[i]);
-        if constexpr (S::kStream)
-          __builtin_nontemporal_store(v, out_pair(i, y, o));
-        else
-          *out_pair(i, y, o) = v;
+        for (int i = 0; i < 9; ++i)
+          *out_pair(i, y, o) = IO::pack(S::encode(fa[i], ra, ws[i]), S::encode(fb[i], rb, ws[i]));
+        *rhat_out_pair(y, o) = IO::pack(ra, rb);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          const W v = IO::make(fa[i], fb[i], sh[i], sh[i]);
+          if constexpr (S::kStream)
+            __builtin_nontemporal_store(v, out_pair(i, y, o));
+          else
+            *out_pair(i, y, o) = v;
+        }
       }
     }
   }
@@ -645,7 +749,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
       St s;
       s.setup(dp, ti, sub, wave, lane);
       const int h = s.h;
-      W w0[9], w1[9];
+      W w0[St::kWords], w1[St::kWords];
       float fa0[9], fb0[9], fa1[9], fb1[9];
       PsiRow p0, p1, p2;
       s.load(-1, w0);
@@ -659,7 +763,8 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
       // psi rows, so six positions per turn need no register copies.
       int r = 0;
       auto pos = [&](float(&fa)[9], float(&fb)[9], float(&fn)[9], float(&gn)[9],
-                     W(&wn)[9], W(&wl)[9], PsiRow& pp, PsiRow& pm, PsiRow& pn) -> bool {
+                     W(&wn)[St::kWords], W(&wl)[St::kWords], PsiRow& pp, PsiRow& pm,
+                     PsiRow& pn) -> bool {
         if constexpr (PF == 2) {
           // wn: loads of row r + 1 already in flight; wl: free for row r + 2
           if (r + 2 <= h) s.load(r + 2, wl);
@@ -735,15 +840,37 @@ __device__ __forceinline__ void pull_cell(const typename S::T* src, size_t n, in
   const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
   const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
   const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-  f[0] = S::load(src + pop_index(0, x, y, nx, ny), ws[0] * rho0);
-  f[1] = S::load(src + pop_index(1, xm, y, nx, ny), ws[1] * rho0);
-  f[2] = S::load(src + pop_index(2, x, ym, nx, ny), ws[2] * rho0);
-  f[3] = S::load(src + pop_index(3, xp, y, nx, ny), ws[3] * rho0);
-  f[4] = S::load(src + pop_index(4, x, yp, nx, ny), ws[4] * rho0);
-  f[5] = S::load(src + pop_index(5, xm, ym, nx, ny), ws[5] * rho0);
-  f[6] = S::load(src + pop_index(6, xp, ym, nx, ny), ws[6] * rho0);
-  f[7] = S::load(src + pop_index(7, xp, yp, nx, ny), ws[7] * rho0);
-  f[8] = S::load(src + pop_index(8, xm, yp, nx, ny), ws[8] * rho0);
+  const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+  const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if constexpr (S::kCellShift)
+      f[i] = S::decode(src[pop_index(i, sx[i], sy[i], nx, ny)],
+                       src[rhat_row(sy[i], nx, ny) + (uint64_t)sx[i]], ws[i]);
+    else
+      f[i] = S::load(src + pop_index(i, sx[i], sy[i], nx, ny), ws[i] * rho0);
+  }
+}
+
+// The nine values a cell stores, A_i(x) for i = 0..8: packed with the global
+// shift, or (per-cell-shift storage) with the cell's own reference density
+// half(sum_i A_i), which is stored beside them.
+template <class S>
+__device__ __forceinline__ void store_cell(typename S::T* dst, int nx, int ny, int x, int y,
+                                           const float (&a)[9], float rho0) {
+  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+  if constexpr (S::kCellShift) {
+    float r = a[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) r += a[i];
+    const typename S::T rh = S::ref(r);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[pop_index(i, x, y, nx, ny)] = S::encode(a[i], rh, ws[i]);
+    dst[rhat_row(y, nx, ny) + (uint64_t)x] = rh;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[pop_index(i, x, y, nx, ny)] = S::pack(a[i], ws[i] * rho0);
+  }
 }
 
 // Moments, pass 1: rho (FP32, the step kernel's summation order).
@@ -807,17 +934,18 @@ __global__ __launch_bounds__(256) void k_set_state(const float* __restrict__ f_i
   const size_t n = (size_t)nx * ny;
   const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
   const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
   for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(c % nx), y = (int)(c / nx);
+    float a[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       int xs = x + ex[i], ys = y + ey[i];
       xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      dst[pop_index(i, x, y, nx, ny)] = S::pack(f_in[i * n + (size_t)ys * nx + xs], ws[i] * rho0);
+      a[i] = f_in[i * n + (size_t)ys * nx + xs];
     }
+    store_cell<S>(dst, nx, ny, x, y, a, rho0);
   }
 }
 
@@ -909,18 +1037,18 @@ __global__ __launch_bounds__(256) void k_init_pop(const double* __restrict__ rho
   const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   const double wd[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
                         1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
-  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
   for (size_t c = blockIdx.x * (size_t)blockDim.x + threadIdx.x; c < n;
        c += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(c % nx), y = (int)(c / nx);
+    float a[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       int xs = x + ex[i], ys = y + ey[i];
       xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
       ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-      const float f = (float)(wd[i] * rho[(size_t)ys * nx + xs]);
-      dst[pop_index(i, x, y, nx, ny)] = S::pack(f, ws[i] * rho0);
+      a[i] = (float)(wd[i] * rho[(size_t)ys * nx + xs]);
     }
+    store_cell<S>(dst, nx, ny, x, y, a, rho0);
   }
 }
 
@@ -1148,15 +1276,27 @@ int grid_for(size_t n, int threads, int cap) {
 
 const StepVariant& step_variant(int v) { return kVariants[v]; }
 
+namespace {
+const void* step_fn(int storage, int variant) {
+  switch (storage) {
+    case 0: return kFn<StoreF32>[variant]();
+    case 1: return kFn<StoreF16S>[variant]();
+    default: return kFn<StoreF16C>[variant]();
+  }
+}
+}  // namespace
+
 hipError_t launch_step(int storage, int variant, const InstDesc* descs, const TileItem* items,
                        const int* nitems, int grid, int sub, hipStream_t st) {
-  if (storage == 0) return kLaunch<StoreF32>[variant](descs, items, nitems, grid, sub, st);
-  return kLaunch<StoreF16S>[variant](descs, items, nitems, grid, sub, st);
+  switch (storage) {
+    case 0: return kLaunch<StoreF32>[variant](descs, items, nitems, grid, sub, st);
+    case 1: return kLaunch<StoreF16S>[variant](descs, items, nitems, grid, sub, st);
+    default: return kLaunch<StoreF16C>[variant](descs, items, nitems, grid, sub, st);
+  }
 }
 
 hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu) {
-  const void* fn = storage == 0 ? kFn<StoreF32>[variant]() : kFn<StoreF16S>[variant]();
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn,
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_fn(storage, variant),
                                                       kVariants[variant].threads, 0);
 }
 
@@ -1175,7 +1315,7 @@ hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
                           const int* nitems, int grid, int sub, int* grab) {
   void* args[] = {(void*)&descs, (void*)&items, (void*)&nitems, (void*)&sub, (void*)&grab};
   hipKernelNodeParams kp{};
-  kp.func = const_cast<void*>(storage == 0 ? kFn<StoreF32>[variant]() : kFn<StoreF16S>[variant]());
+  kp.func = const_cast<void*>(step_fn(storage, variant));
   kp.gridDim = dim3(grid);
   kp.blockDim = dim3(kVariants[variant].threads);
   kp.sharedMemBytes = 0;
@@ -1199,48 +1339,51 @@ hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
   return hipGraphAddKernelNode(node, g, deps, nd, &kp);
 }
 
+// Calls f with a value of the storage trait numbered `storage` (LBM_F32,
+// LBM_F16_SHIFTED, LBM_F16_CELL).
+template <class F>
+hipError_t with_storage(int storage, F&& f) {
+  switch (storage) {
+    case 0: return f(StoreF32{});
+    case 1: return f(StoreF16S{});
+    default: return f(StoreF16C{});
+  }
+}
+
 hipError_t launch_moments(int storage, const void* src, int nx, int ny, float rho0, float G,
                           float* rho, float* ux, float* uy, hipStream_t st) {
-  const size_t n = (size_t)nx * ny;
-  const int g = grid_for(n, 256, 8192);
-  if (storage == 0) {
-    hipLaunchKernelGGL(k_rho32<StoreF32>, dim3(g), dim3(256), 0, st, (const float*)src, nx, ny,
-                       rho0, rho);
+  const int g = grid_for((size_t)nx * ny, 256, 8192);
+  return with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    using T = typename S::T;
+    hipLaunchKernelGGL(k_rho32<S>, dim3(g), dim3(256), 0, st, (const T*)src, nx, ny, rho0, rho);
     if (ux || uy)
-      hipLaunchKernelGGL(k_velocity<StoreF32>, dim3(g), dim3(256), 0, st, (const float*)src, nx,
-                         ny, rho0, G, (const float*)rho, ux, uy);
-  } else {
-    hipLaunchKernelGGL(k_rho32<StoreF16S>, dim3(g), dim3(256), 0, st, (const _Float16*)src, nx,
-                       ny, rho0, rho);
-    if (ux || uy)
-      hipLaunchKernelGGL(k_velocity<StoreF16S>, dim3(g), dim3(256), 0, st, (const _Float16*)src,
-                         nx, ny, rho0, G, (const float*)rho, ux, uy);
-  }
-  return hipGetLastError();
+      hipLaunchKernelGGL(k_velocity<S>, dim3(g), dim3(256), 0, st, (const T*)src, nx, ny, rho0, G,
+                         (const float*)rho, ux, uy);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_get_state(int storage, const void* src, int nx, int ny, float rho0, float* f,
                             hipStream_t st) {
   const int g = grid_for((size_t)nx * ny, 256, 8192);
-  if (storage == 0)
-    hipLaunchKernelGGL(k_get_state<StoreF32>, dim3(g), dim3(256), 0, st, (const float*)src, nx,
+  return with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(k_get_state<S>, dim3(g), dim3(256), 0, st, (const typename S::T*)src, nx,
                        ny, rho0, f);
-  else
-    hipLaunchKernelGGL(k_get_state<StoreF16S>, dim3(g), dim3(256), 0, st, (const _Float16*)src,
-                       nx, ny, rho0, f);
-  return hipGetLastError();
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_set_state(int storage, const float* f, int nx, int ny, float rho0, void* dst,
                             hipStream_t st) {
   const int g = grid_for((size_t)nx * ny, 256, 8192);
-  if (storage == 0)
-    hipLaunchKernelGGL(k_set_state<StoreF32>, dim3(g), dim3(256), 0, st, f, nx, ny, rho0,
-                       (float*)dst);
-  else
-    hipLaunchKernelGGL(k_set_state<StoreF16S>, dim3(g), dim3(256), 0, st, f, nx, ny, rho0,
-                       (_Float16*)dst);
-  return hipGetLastError();
+  return with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(k_set_state<S>, dim3(g), dim3(256), 0, st, f, nx, ny, rho0,
+                       (typename S::T*)dst);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs& a, double* rho64,
@@ -1250,24 +1393,24 @@ hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs&
   const int g = (int)std::min<size_t>(tiles, 16384);
   hipLaunchKernelGGL(k_init_rho, dim3(g), dim3(256), 0, st, drops, nd, a, rho64);
   const int g2 = grid_for(n, 256, 8192);
-  if (storage == 0)
-    hipLaunchKernelGGL(k_init_pop<StoreF32>, dim3(g2), dim3(256), 0, st, (const double*)rho64,
-                       a.nx, a.ny, rho0, (float*)dst);
-  else
-    hipLaunchKernelGGL(k_init_pop<StoreF16S>, dim3(g2), dim3(256), 0, st, (const double*)rho64,
-                       a.nx, a.ny, rho0, (_Float16*)dst);
-  return hipGetLastError();
+  return with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(k_init_pop<S>, dim3(g2), dim3(256), 0, st, (const double*)rho64, a.nx, a.ny,
+                       rho0, (typename S::T*)dst);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, float rho0,
                               double* rho64, double* partials, double* out, hipStream_t st) {
   const int g = grid_for((size_t)nx * ny, kRedThreads, kMaxPartials);
-  if (storage == 0)
-    hipLaunchKernelGGL(k_diag_rho<StoreF32>, dim3(g), dim3(kRedThreads), 0, st, (const float*)src,
+  const hipError_t e = with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(k_diag_rho<S>, dim3(g), dim3(kRedThreads), 0, st, (const typename S::T*)src,
                        nx, ny, rho0, rho64, partials);
-  else
-    hipLaunchKernelGGL(k_diag_rho<StoreF16S>, dim3(g), dim3(kRedThreads), 0, st,
-                       (const _Float16*)src, nx, ny, rho0, rho64, partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_grad, dim3(g), dim3(kRedThreads), 0, st, (const double*)rho64, nx, ny,
                      partials);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, g,
@@ -1278,12 +1421,13 @@ hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, floa
 hipError_t launch_step_diag(int storage, const InstDesc* descs, const TileItem* items,
                             const int* nitems, int grid, int sub, double* partials,
                             double* out, hipStream_t st) {
-  if (storage == 0)
-    hipLaunchKernelGGL(k_step_diag<StoreF32>, dim3(grid), dim3(kDiagThreads), 0, st, descs, items,
-                       nitems, sub, partials);
-  else
-    hipLaunchKernelGGL(k_step_diag<StoreF16S>, dim3(grid), dim3(kDiagThreads), 0, st, descs, items,
-                       nitems, sub, partials);
+  const hipError_t e = with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(k_step_diag<S>, dim3(grid), dim3(kDiagThreads), 0, st, descs, items, nitems,
+                       sub, partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, grid,
                      out);
   return hipGetLastError();

@@ -44,15 +44,17 @@ lbm_status validate_params(const lbm_params* p) {
     return fail(LBM_EINVAL, "grid too large (9 nx ny must be < 2^32)");
   if (!std::isfinite(p->G)) return fail(LBM_EINVAL, "G must be finite");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
-  if (p->storage != LBM_F32 && p->storage != LBM_F16_SHIFTED)
-    return fail(LBM_EINVAL, "storage must be LBM_F32 or LBM_F16_SHIFTED");
+  if (p->storage != LBM_F32 && p->storage != LBM_F16_SHIFTED && p->storage != LBM_F16_CELL)
+    return fail(LBM_EINVAL, "storage must be LBM_F32, LBM_F16_SHIFTED or LBM_F16_CELL");
   if (p->storage == LBM_F16_SHIFTED && (!std::isfinite(p->rho0) || p->rho0 < 0.0))
     return fail(LBM_EINVAL, "rho0 must be finite and >= 0");
   return LBM_OK;
 }
 
 size_t pop_bytes_for(const lbm_params& p) {
-  return 9ull * (size_t)p.nx * (size_t)p.ny * (p.storage == LBM_F32 ? 4 : 2);
+  // per-cell-shift storage keeps a tenth plane (the reference density)
+  const size_t planes = p.storage == LBM_F16_CELL ? 10 : 9;
+  return planes * (size_t)p.nx * (size_t)p.ny * (p.storage == LBM_F32 ? 4 : 2);
 }
 
 WorkLayout work_layout(int nx, int ny) {
@@ -114,7 +116,7 @@ int default_strip_tile(const lbm_params& p) {
   // variant index * kNumRows + row index; see kVariants / kRowChoices.
   if (p.nx <= 64) return 0 * kNumRows + 0;   // 64 threads, 1 cell, 8 rows
   if (p.nx <= 128) return 2 * kNumRows + 1;  // 128 threads, 16 rows
-  if (p.storage == LBM_F16_SHIFTED)
+  if (p.storage != LBM_F32)
     return 9 * kNumRows + 2;                 // 256 threads x 2 cells, 32 rows
   return 8 * kNumRows + 0;                   // 256 threads, 2 rows in flight, 8 rows
 }
@@ -122,7 +124,7 @@ int default_strip_tile(const lbm_params& p) {
 int default_tile(const lbm_params& p) {
   // FP16-shifted storage: paired columns, 4 wavefronts, 2 rows in flight,
   // 8-row bands, where the grid allows it.
-  if (p.storage == LBM_F16_SHIFTED) {
+  if (p.storage != LBM_F32) {
     const int k = find_variant(256, 2, 2, 1) * kNumRows + 0;
     if (tile_valid(k, p.nx)) return k;
   }
@@ -358,16 +360,17 @@ hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
                           int ncounters);
 hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t st);
 
-size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[2], int K) {
+size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[kNumStorages], int K) {
   size_t o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
-  o += align_up((size_t)2 * K * sizeof(int), 256);  // work counters
-  for (int s = 0; s < 2; ++s) o += 256 + align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
+  o += align_up((size_t)kNumStorages * K * sizeof(int), 256);  // work counters
+  for (int s = 0; s < kNumStorages; ++s)
+    o += 256 + align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
   return o;
 }
 
 lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
-                             const int cap_items_[2], const int variants[2], void* work,
-                             size_t wbytes) {
+                             const int cap_items_[kNumStorages],
+                             const int variants[kNumStorages], void* work, size_t wbytes) {
   stream = st;
   K = steps_per_tick;
   cap_inst = cap_inst_;
@@ -377,9 +380,9 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   d_desc = reinterpret_cast<InstDesc*>(w);
   o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
   d_counters = reinterpret_cast<int*>(w + o);
-  o += align_up((size_t)2 * K * sizeof(int), 256);
+  o += align_up((size_t)kNumStorages * K * sizeof(int), 256);
   const int cus = device_cu_count();
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < kNumStorages; ++s) {
     cap_items[s] = cap_items_[s];
     variant[s] = variants[s];
     d_nitems[s] = reinterpret_cast<int*>(w + o);
@@ -398,7 +401,7 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   }
   SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc), (size_t)cap_inst * sizeof(InstDesc),
                           hipHostMallocDefault));
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < kNumStorages; ++s)
     if (cap_items[s] > 0)
       SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_items[s]),
                               (size_t)cap_items[s] * sizeof(TileItem) + 64,
@@ -407,13 +410,15 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   // Graph: tick_begin -> K x (one persistent step launch per storage type) -> tick_end.
   SCLBM_HIP(hipGraphCreate(&graph, 0));
   hipGraphNode_t prev;
-  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K, d_counters, 2 * K));
+  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K, d_counters,
+                           kNumStorages * K));
   for (int j = 0; j < K; ++j)
-    for (int s = 0; s < 2; ++s) {
+    for (int s = 0; s < kNumStorages; ++s) {
       if (grid[s] == 0) continue;
       hipGraphNode_t node;
       SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, variant[s], d_desc, d_items[s],
-                               d_nitems[s], grid[s], j, dynamic ? d_counters + 2 * j + s : nullptr));
+                               d_nitems[s], grid[s], j,
+                               dynamic ? d_counters + kNumStorages * j + s : nullptr));
       prev = node;
     }
   hipGraphNode_t last;
@@ -427,7 +432,7 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
   if ((int)m.size() > cap_inst) return fail(LBM_EINVAL, "too many batch members");
   // The staging buffers may still feed the previous upload.
   if (staged_pending) SCLBM_HIP(hipEventSynchronize(staged));
-  int count[2] = {0, 0};
+  int count[kNumStorages] = {};
   for (int i = 0; i < cap_inst; ++i) {
     InstDesc d{};
     d.nsub = 0;
@@ -451,7 +456,7 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
   }
   SCLBM_HIP(hipMemcpyAsync(d_desc, h_desc, (size_t)cap_inst * sizeof(InstDesc),
                            hipMemcpyHostToDevice, stream));
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < kNumStorages; ++s) {
     if (cap_items[s] == 0) continue;
     std::vector<TileItem> v(h_items[s], h_items[s] + count[s]);
     v = xcd_order(v);
@@ -485,13 +490,13 @@ void BatchEngine::destroy() {
   if (graph) (void)hipGraphDestroy(graph);
   if (staged) (void)hipEventDestroy(staged);
   if (h_desc) (void)hipHostFree(h_desc);
-  for (int s = 0; s < 2; ++s)
+  for (int s = 0; s < kNumStorages; ++s)
     if (h_items[s]) (void)hipHostFree(h_items[s]);
   exec = nullptr;
   graph = nullptr;
   staged = nullptr;
   h_desc = nullptr;
-  h_items[0] = h_items[1] = nullptr;
+  for (int s = 0; s < kNumStorages; ++s) h_items[s] = nullptr;
 }
 
 // Tile a member uses inside a batch: the batch's override if set, else the
@@ -543,13 +548,13 @@ struct lbm_batch {
 namespace {
 
 struct BatchShape {
-  int variants[2];
-  int items[2];
+  int variants[kNumStorages];
+  int items[kNumStorages];
 };
 
 BatchShape batch_shape(const std::vector<lbm_ctx*>& m, int tile_override = -1) {
   BatchShape b{};
-  for (int s = 0; s < 2; ++s) {
+  for (int s = 0; s < kNumStorages; ++s) {
     b.variants[s] = pick_variant(m, s);
     if (b.variants[s] >= 0 && tile_override >= 0) b.variants[s] = tile_variant(tile_override);
     b.items[s] = b.variants[s] < 0 ? 0 : count_items(m, s, b.variants[s], tile_override);
@@ -920,7 +925,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
     BatchEngine& g = b->eng;
     auto launch_all = [&]() {
       hipError_t e = hipSuccess;
-      for (int s = 0; s < 2 && e == hipSuccess; ++s)
+      for (int s = 0; s < kNumStorages && e == hipSuccess; ++s)
         if (g.grid[s] > 0)
           e = launch_step(s, g.variant[s], g.d_desc, g.d_items[s], g.d_nitems[s], g.grid[s], 0,
                           g.stream);

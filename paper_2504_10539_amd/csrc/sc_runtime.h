@@ -80,7 +80,8 @@ int device_cu_count();
 struct BatchEngine {
   hipStream_t stream = nullptr;
   int K = 1, cap_inst = 0;
-  int cap_items[2] = {0, 0}, variant[2] = {-1, -1}, grid[2] = {0, 0}, nitems[2] = {0, 0};
+  int cap_items[kNumStorages] = {}, variant[kNumStorages] = {-1, -1, -1},
+      grid[kNumStorages] = {}, nitems[kNumStorages] = {};
   InstDesc* d_desc = nullptr;
   int* d_counters = nullptr;  // 2 K work counters, zeroed by the tick-begin kernel
   // Grid sized to the resident capacity, looping over the items (needed when
@@ -89,19 +90,20 @@ struct BatchEngine {
   // Items taken from the work counters instead of the static order that keeps
   // neighbouring bands on one XCD.
   bool dynamic = false;
-  int* d_nitems[2] = {nullptr, nullptr};
-  TileItem* d_items[2] = {nullptr, nullptr};
+  int* d_nitems[kNumStorages] = {};
+  TileItem* d_items[kNumStorages] = {};
   InstDesc* h_desc = nullptr;
-  TileItem* h_items[2] = {nullptr, nullptr};
+  TileItem* h_items[kNumStorages] = {};
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<lbm_ctx*> members;
 
-  static size_t work_bytes(int cap_inst, const int cap_items[2], int K);
-  lbm_status init(hipStream_t st, int steps_per_tick, int cap_inst, const int cap_items[2],
-                  const int variants[2], void* work, size_t wbytes);
+  static size_t work_bytes(int cap_inst, const int cap_items[kNumStorages], int K);
+  lbm_status init(hipStream_t st, int steps_per_tick, int cap_inst,
+                  const int cap_items[kNumStorages], const int variants[kNumStorages], void* work,
+                  size_t wbytes);
   // Tile used for every member instead of the members' own (-1: none).
   int tile_override = -1;
   // Uploads the members' descriptors (with `remaining` steps each, and nsub

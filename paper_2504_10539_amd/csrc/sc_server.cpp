@@ -475,9 +475,9 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
     const int sw = tile_width(v * kNumRows);
     const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
                                           1u << 22);
-    const int cap_items[2] = {per, per};
+    const int cap_items[kNumStorages] = {per, per, per};
     const int v16 = tile_variant(default_strip_tile(lbm_params{2048, 2048, -5.0, 1.0, 1, 1.0}));
-    const int variants[2] = {v, v16};
+    const int variants[kNumStorages] = {v, v16, v16};
     eng_bytes = align_up(BatchEngine::work_bytes(opts->max_slots, cap_items, opts->steps_per_tick), 256);
     if (eng_bytes >= pool_bytes / 2) {
       delete s;

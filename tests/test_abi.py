@@ -78,6 +78,9 @@ def test_buffer_sizes_and_validation(lbm):
     p16 = lbm.make_params(100, 60, -5.0, 1.0, lbm.LBM_F16_SHIFTED, 0.5)
     assert lbm.LIB.lbm_buffer_bytes(ctypes.byref(p16), ctypes.byref(pop), None) == 0
     assert pop.value == 9 * 100 * 60 * 2
+    pc = lbm.make_params(100, 60, -5.0, 1.0, lbm.LBM_F16_CELL)
+    assert lbm.LIB.lbm_buffer_bytes(ctypes.byref(pc), ctypes.byref(pop), None) == 0
+    assert pop.value == 10 * 100 * 60 * 2  # nine population planes and the reference plane
     bad = [lbm.make_params(0, 60, -5.0, 1.0), lbm.make_params(10, 10, -5.0, 0.5),
            lbm.make_params(10, 10, float("nan"), 1.0), lbm.make_params(10, 10, -5.0, 1.0, 7),
            lbm.make_params(10, 10, -5.0, 1.0, lbm.LBM_F16_SHIFTED, -1.0),

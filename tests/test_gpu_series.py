@@ -33,6 +33,7 @@ def _pair(nx, ny, G, tau, storage, drops, seed):
     (64, 64, -5.0, 1.0, 0, 100, 10),
     (300, 77, -5.2, 0.9, 0, 37, 5),
     (96, 40, -5.5, 1.0, 1, 30, 3),
+    (130, 40, -5.5, 1.0, 2, 30, 4),
     (64, 64, -5.0, 1.0, 0, 600, 2),   # more records than the device keeps between copies
 ])
 def test_series_matches_separate_metrics(nx, ny, G, tau, storage, n, every):

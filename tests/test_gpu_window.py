@@ -36,10 +36,12 @@ def test_many_droplet_window_error_series(nthreads):
     drops = inputs.many_droplets(4096, 2000, 8, 48, seed=3)
     f = oracle.droplet_state(n, n, drops, seed=3, period=(4096, 4096))
     sims = {"f32": L.Simulation(n, n, G, tau, L.LBM_F32),
-            "f16": L.Simulation(n, n, G, tau, L.LBM_F16_SHIFTED, 1.0)}
+            "f16": L.Simulation(n, n, G, tau, L.LBM_F16_SHIFTED, 1.0),
+            "f16c": L.Simulation(n, n, G, tau, L.LBM_F16_CELL)}
     for s in sims.values():
         s.init_droplets(drops, seed=3, period=(4096, 4096))
-    worst = {"f32_cell": 0.0, "f32_range": 0.0, "f32_metric": 0.0, "f16_metric": 0.0}
+    worst = {"f32_cell": 0.0, "f32_range": 0.0, "f32_metric": 0.0, "f16_metric": 0.0,
+             "f16c_metric": 0.0, "f16c_range": 0.0}
     for seg in range(1, 11):
         f = oracle.step(f, G, tau, 500, nthreads)
         rr = oracle.density(f)
@@ -58,10 +60,15 @@ def test_many_droplet_window_error_series(nthreads):
                 worst["f32_cell"] = max(worst["f32_cell"], cell)
                 worst["f32_range"] = max(worst["f32_range"], rng)
                 worst["f32_metric"] = max(worst["f32_metric"], met)
-            else:
+            elif name == "f16":
                 worst["f16_metric"] = max(worst["f16_metric"], met)
+            else:
+                worst["f16c_metric"] = max(worst["f16c_metric"], met)
+                worst["f16c_range"] = max(worst["f16c_range"], rng)
         print(" | ".join(line))
     # regression bounds over the measured series, with margin
     assert worst["f32_cell"] < 2e-4 and worst["f32_range"] < 6e-5, worst
     assert worst["f32_metric"] < 1e-4, worst
     assert worst["f16_metric"] < 0.02, worst
+    assert worst["f16c_metric"] < 0.02, worst
+    print("worst", worst)
