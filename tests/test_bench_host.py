@@ -46,11 +46,12 @@ def test_committed_counters_name_real_shapes(lbm):
     with open(os.path.join(ROOT, "profiles", "step_counters.json")) as fh:
         d = json.load(fh)
     shapes = {(bench.kernel_name(lbm, t["id"], s), t["width"], t["rows"])
-              for t in lbm.tiles() for s in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED)}
+              for t in lbm.tiles() for s in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL)}
     assert d["entries"]
     for e in d["entries"]:
         assert (e["kernel"], e["width"], e["rows"]) in shapes, e
-        assert e["bytes_per_launch"] > 0.9 * {"f32": 72, "f16_shifted": 36}[e["storage"]] * e["n"] ** 2
+        bpu = {"f32": 72, "f16_shifted": 36, "f16_cell": 40}[e["storage"]]
+        assert e["bytes_per_launch"] > 0.9 * bpu * e["n"] ** 2
 
 
 def test_more_than_one_gpu_is_refused():
