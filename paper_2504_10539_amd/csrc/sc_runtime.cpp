@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <fstream>
+#include <map>
 #include <mutex>
 #include <sstream>
 #include <string>
@@ -112,33 +113,60 @@ std::vector<TileItem> xcd_order(const std::vector<TileItem>& items) {
   return out;
 }
 
+int row_choice(int rows) {
+  for (int r = 0; r < kNumRows; ++r)
+    if (kRowChoices[r] == rows) return r;
+  return 0;
+}
+
+// Default shapes from measurements on MI355X: long bands once the grid alone
+// fills the GPU (4096^2: 64 rows), short ones when it does not (1024^2: 4
+// rows, 512^2 and below: 2 rows); the widest strip the grid can use.
 int default_strip_tile(const lbm_params& p) {
-  // variant index * kNumRows + row index; see kVariants / kRowChoices.
-  if (p.nx <= 64) return 0 * kNumRows + 0;   // 64 threads, 1 cell, 8 rows
-  if (p.nx <= 128) return 2 * kNumRows + 1;  // 128 threads, 16 rows
-  if (p.storage != LBM_F32)
-    return 9 * kNumRows + 2;                 // 256 threads x 2 cells, 32 rows
-  return 8 * kNumRows + 0;                   // 256 threads, 2 rows in flight, 8 rows
+  const size_t cells = (size_t)p.nx * (size_t)p.ny;
+  const int rows = cells >= (4u << 20) ? 64 : (cells >= (1u << 20) ? 4 : 2);
+  int v;
+  if (p.storage != LBM_F32 && p.nx > 128)
+    v = find_variant(256, 2, 1, 0);  // 512 columns, two cells per thread
+  else if (p.nx >= 512)
+    v = find_variant(512, 1, 2, 0);
+  else if (p.nx >= 256)
+    v = find_variant(256, 1, 2, 0);
+  else if (p.nx >= 128)
+    v = find_variant(128, 1, 2, 0);
+  else
+    v = find_variant(64, 1, 1, 0);
+  return v * kNumRows + row_choice(rows);
 }
 
 int default_tile(const lbm_params& p) {
-  // FP16-shifted storage: paired columns, 4 wavefronts, 2 rows in flight,
-  // 8-row bands, where the grid allows it.
+  // FP16 storage: paired columns, 4 wavefronts, 2 rows in flight, 4-row
+  // bands (2 below a million cells), where the grid allows it.
   if (p.storage != LBM_F32) {
-    const int k = find_variant(256, 2, 2, 1) * kNumRows + 0;
+    const size_t cells = (size_t)p.nx * (size_t)p.ny;
+    const int k = find_variant(256, 2, 2, 1) * kNumRows + row_choice(cells >= (1u << 20) ? 4 : 2);
     if (tile_valid(k, p.nx)) return k;
   }
   return default_strip_tile(p);
 }
 
+// Architecture name of the current device, looked up once per device
+// (hipGetDeviceProperties is slow enough to matter per created run).
 std::string device_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> known;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return "unknown";
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = known.find(dev);
+  if (it != known.end()) return it->second;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
   std::string a = prop.gcnArchName;
   const size_t c = a.find(':');
-  return c == std::string::npos ? a : a.substr(0, c);
+  a = c == std::string::npos ? a : a.substr(0, c);
+  known[dev] = a;
+  return a;
 }
 
 int device_cu_count() {
@@ -399,14 +427,17 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
     const int cap = std::max(8, std::max(occ, 1) * cus / 8 * 8);
     grid[s] = persistent ? std::min(cap_items[s], cap) : cap_items[s];
   }
-  SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc), (size_t)cap_inst * sizeof(InstDesc),
-                          hipHostMallocDefault));
+  for (int b = 0; b < 2; ++b)
+    SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc[b]),
+                            (size_t)cap_inst * sizeof(InstDesc), hipHostMallocDefault));
   for (int s = 0; s < kNumStorages; ++s)
     if (cap_items[s] > 0)
-      SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_items[s]),
-                              (size_t)cap_items[s] * sizeof(TileItem) + 64,
-                              hipHostMallocDefault));
-  SCLBM_HIP(hipEventCreateWithFlags(&staged, hipEventDisableTiming));
+      for (int b = 0; b < 2; ++b)
+        SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_items[s][b]),
+                                (size_t)cap_items[s] * sizeof(TileItem) + 64,
+                                hipHostMallocDefault));
+  for (int b = 0; b < 2; ++b)
+    SCLBM_HIP(hipEventCreateWithFlags(&staged[b], hipEventDisableTiming));
   // Graph: tick_begin -> K x (one persistent step launch per storage type) -> tick_end.
   SCLBM_HIP(hipGraphCreate(&graph, 0));
   hipGraphNode_t prev;
@@ -430,8 +461,12 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
 lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining,
                              int nsub_init) {
   if ((int)m.size() > cap_inst) return fail(LBM_EINVAL, "too many batch members");
-  // The staging buffers may still feed the previous upload.
-  if (staged_pending) SCLBM_HIP(hipEventSynchronize(staged));
+  // Two sets of staging buffers alternate: this load may reuse a set only
+  // once the upload that last read it has run.
+  const int sb = stage;
+  stage ^= 1;
+  if (staged_pending[sb]) SCLBM_HIP(hipEventSynchronize(staged[sb]));
+  InstDesc* hd = h_desc[sb];
   int count[kNumStorages] = {};
   for (int i = 0; i < cap_inst; ++i) {
     InstDesc d{};
@@ -446,31 +481,33 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
       const int s = c->p.storage;
       if (grid[s] == 0) return fail(LBM_EINVAL, "batch has no kernel for this storage type");
       std::vector<TileItem> items;
-      make_items(c->p.nx, c->p.ny, member_tile(c, variant[s], tile_override), i, items);
+      make_items(c->p.nx, c->p.ny, member_tile(c, variant[s], tile_override, row_override), i,
+                 items);
       if (count[s] + (int)items.size() > cap_items[s])
         return fail(LBM_ENOMEM, "batch tile table full");
-      std::copy(items.begin(), items.end(), h_items[s] + count[s]);
+      std::copy(items.begin(), items.end(), h_items[s][sb] + count[s]);
       count[s] += (int)items.size();
     }
-    h_desc[i] = d;
+    hd[i] = d;
   }
-  SCLBM_HIP(hipMemcpyAsync(d_desc, h_desc, (size_t)cap_inst * sizeof(InstDesc),
+  SCLBM_HIP(hipMemcpyAsync(d_desc, hd, (size_t)cap_inst * sizeof(InstDesc),
                            hipMemcpyHostToDevice, stream));
   for (int s = 0; s < kNumStorages; ++s) {
     if (cap_items[s] == 0) continue;
-    std::vector<TileItem> v(h_items[s], h_items[s] + count[s]);
+    TileItem* hi = h_items[s][sb];
+    std::vector<TileItem> v(hi, hi + count[s]);
     v = xcd_order(v);
-    std::copy(v.begin(), v.end(), h_items[s]);
-    int* hn = reinterpret_cast<int*>(h_items[s] + cap_items[s]);
+    std::copy(v.begin(), v.end(), hi);
+    int* hn = reinterpret_cast<int*>(hi + cap_items[s]);
     *hn = count[s];
     nitems[s] = count[s];
     if (count[s] > 0)
-      SCLBM_HIP(hipMemcpyAsync(d_items[s], h_items[s], (size_t)count[s] * sizeof(TileItem),
+      SCLBM_HIP(hipMemcpyAsync(d_items[s], hi, (size_t)count[s] * sizeof(TileItem),
                                hipMemcpyHostToDevice, stream));
     SCLBM_HIP(hipMemcpyAsync(d_nitems[s], hn, sizeof(int), hipMemcpyHostToDevice, stream));
   }
-  SCLBM_HIP(hipEventRecord(staged, stream));
-  staged_pending = true;
+  SCLBM_HIP(hipEventRecord(staged[sb], stream));
+  staged_pending[sb] = true;
   members = m;
   return LBM_OK;
 }
@@ -488,21 +525,27 @@ lbm_status BatchEngine::replay() {
 void BatchEngine::destroy() {
   if (exec) (void)hipGraphExecDestroy(exec);
   if (graph) (void)hipGraphDestroy(graph);
-  if (staged) (void)hipEventDestroy(staged);
-  if (h_desc) (void)hipHostFree(h_desc);
+  for (int b = 0; b < 2; ++b) {
+    if (staged[b]) (void)hipEventDestroy(staged[b]);
+    if (h_desc[b]) (void)hipHostFree(h_desc[b]);
+    staged[b] = nullptr;
+    h_desc[b] = nullptr;
+    staged_pending[b] = false;
+  }
   for (int s = 0; s < kNumStorages; ++s)
-    if (h_items[s]) (void)hipHostFree(h_items[s]);
+    for (int b = 0; b < 2; ++b)
+      if (h_items[s][b]) (void)hipHostFree(h_items[s][b]);
   exec = nullptr;
   graph = nullptr;
-  staged = nullptr;
-  h_desc = nullptr;
-  for (int s = 0; s < kNumStorages; ++s) h_items[s] = nullptr;
+  for (int s = 0; s < kNumStorages; ++s) h_items[s][0] = h_items[s][1] = nullptr;
 }
 
 // Tile a member uses inside a batch: the batch's override if set, else the
-// batch's strip variant with the member's own band height.
-int member_tile(const lbm_ctx* c, int variant, int tile_override) {
-  return tile_override >= 0 ? tile_override : variant * kNumRows + (c->tile % kNumRows);
+// batch's strip variant with the batch's band height if set, else the
+// member's own.
+int member_tile(const lbm_ctx* c, int variant, int tile_override, int row_override) {
+  if (tile_override >= 0) return tile_override;
+  return variant * kNumRows + (row_override >= 0 ? row_override : c->tile % kNumRows);
 }
 
 // Strip variant used for one storage type: that of the widest member's tile.
@@ -528,9 +571,9 @@ int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int ti
   int n = 0;
   for (lbm_ctx* c : m) {
     if (c->p.storage != storage) continue;
-    std::vector<TileItem> items;
-    make_items(c->p.nx, c->p.ny, member_tile(c, variant, tile_override), 0, items);
-    n += (int)items.size();
+    const int k = member_tile(c, variant, tile_override);  // as make_items tiles it
+    const int sw = tile_width(k), rows = tile_rows(k);
+    n += ((c->p.nx + sw - 1) / sw) * ((c->p.ny + rows - 1) / rows);
   }
   return n;
 }
@@ -576,29 +619,29 @@ lbm_status batch_rebuild(lbm_batch* b, int tile_override, int nsub_init) {
   return r;
 }
 
-// Largest item counts over every tile shape (64-column strips, 8-row bands).
-BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) { return batch_shape(m, 0); }
+// Largest item counts over every tile shape the members can run.
+BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) {
+  BatchShape b = batch_shape(m);
+  for (int k = 0; k < kNumTiles; ++k) {
+    bool valid = true;
+    for (lbm_ctx* c : m) valid = valid && tile_valid(k, c->p.nx);
+    if (!valid) continue;
+    const BatchShape t = batch_shape(m, k);
+    for (int s = 0; s < kNumStorages; ++s) b.items[s] = std::max(b.items[s], t.items[s]);
+  }
+  return b;
+}
 
 }  // namespace
 
 // ------------------------------------------------------------------ C-ABI
 
-extern "C" {
-
-const char* lbm_last_error(void) { return g_error.c_str(); }
-
-const char* lbm_version(void) { return "sclbm 0.1 (gfx950)"; }
-
-lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes) {
-  const lbm_status s = validate_params(p);
-  if (s != LBM_OK) return s;
-  if (pop_bytes) *pop_bytes = pop_bytes_for(*p);
-  if (work_bytes) *work_bytes = work_layout(p->nx, p->ny).total;
-  return LBM_OK;
-}
-
-lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_bytes, void* work,
-                      size_t work_bytes, void* hip_stream, lbm_ctx** out) {
+// standalone = false: a run driven only by a batch engine (the server's
+// continuous policy), which keeps its own descriptor and tile tables; the
+// run's own are not uploaded, so creating it does not wait for the stream.
+lbm_status sclbm::create_ctx(const lbm_params* p, void* popA, void* popB, size_t pop_bytes,
+                             void* work, size_t work_bytes, void* hip_stream, bool standalone,
+                             lbm_ctx** out) {
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
   lbm_status s = validate_params(p);
@@ -631,6 +674,11 @@ lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_by
   c->d_spartials = reinterpret_cast<double*>(w + lay.s_partials);
   c->d_srecords = reinterpret_cast<double*>(w + lay.s_records);
   c->arch = device_arch();
+  if (!standalone) {
+    c->tile = default_tile(*p);  // its band height is what a batch may use
+    *out = c;
+    return LBM_OK;
+  }
   const InstDesc d = c->host_desc();
   hipError_t e = hipMemcpyAsync(c->d_desc, &d, sizeof d, hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -649,17 +697,10 @@ lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_by
   return LBM_OK;
 }
 
-lbm_status lbm_destroy(lbm_ctx* c) {
-  if (!c) return LBM_OK;
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  const hipError_t e = hipStreamSynchronize(c->stream);
-  if (c->h_result) (void)hipHostFree(c->h_result);
-  if (c->h_series) (void)hipHostFree(c->h_series);
-  delete c;
-  return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
-}
-
-lbm_status lbm_init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip) {
+// sync = false: returns after enqueueing; the caller keeps `drops` alive
+// until the stream has passed the initialisation.
+lbm_status sclbm::init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip,
+                                bool sync) {
   if (!c || !ip) return fail(LBM_EINVAL, "ctx or init is NULL");
   if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
   if (n < 0 || (n > 0 && !drops)) return fail(LBM_EINVAL, "bad droplet array");
@@ -703,10 +744,43 @@ lbm_status lbm_init_droplets(lbm_ctx* c, const double* drops, int32_t n, const l
                              c->stream));
   SCLBM_HIP(launch_init(c->p.storage, d_drops, n, a, rho64, c->host_desc().rho0, c->pop[0],
                         c->stream));
-  SCLBM_HIP(hipStreamSynchronize(c->stream));
+  if (sync) SCLBM_HIP(hipStreamSynchronize(c->stream));
   c->parity = 0;
   c->steps = 0;
   return LBM_OK;
+}
+
+extern "C" {
+
+const char* lbm_last_error(void) { return g_error.c_str(); }
+
+const char* lbm_version(void) { return "sclbm 0.1 (gfx950)"; }
+
+lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes) {
+  const lbm_status s = validate_params(p);
+  if (s != LBM_OK) return s;
+  if (pop_bytes) *pop_bytes = pop_bytes_for(*p);
+  if (work_bytes) *work_bytes = work_layout(p->nx, p->ny).total;
+  return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_bytes, void* work,
+                      size_t work_bytes, void* hip_stream, lbm_ctx** out) {
+  return sclbm::create_ctx(p, popA, popB, pop_bytes, work, work_bytes, hip_stream, true, out);
+}
+
+lbm_status lbm_destroy(lbm_ctx* c) {
+  if (!c) return LBM_OK;
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  const hipError_t e = hipStreamSynchronize(c->stream);
+  if (c->h_result) (void)hipHostFree(c->h_result);
+  if (c->h_series) (void)hipHostFree(c->h_series);
+  delete c;
+  return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+lbm_status lbm_init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip) {
+  return sclbm::init_droplets(c, drops, n, ip, true);
 }
 
 lbm_status lbm_step_n(lbm_ctx* c, int64_t n) {

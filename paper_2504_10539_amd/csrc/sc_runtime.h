@@ -68,6 +68,8 @@ WorkLayout work_layout(int nx, int ny);
 // variant, so it is valid for every grid width.
 int default_tile(const lbm_params& p);
 int default_strip_tile(const lbm_params& p);
+// Index of a band height in kRowChoices (0 if it is not one).
+int row_choice(int rows);
 int tuned_tile(const lbm_params& p, const std::string& arch);  // -1 if none
 void record_tuned_tile(const lbm_params& p, const std::string& arch, int tile, double ms);
 std::string device_arch();
@@ -92,10 +94,12 @@ struct BatchEngine {
   bool dynamic = false;
   int* d_nitems[kNumStorages] = {};
   TileItem* d_items[kNumStorages] = {};
-  InstDesc* h_desc = nullptr;
-  TileItem* h_items[kNumStorages] = {};
-  hipEvent_t staged = nullptr;
-  bool staged_pending = false;
+  // pinned staging of the tables, two sets used in turn (stage = next set)
+  InstDesc* h_desc[2] = {};
+  TileItem* h_items[kNumStorages][2] = {};
+  hipEvent_t staged[2] = {};
+  bool staged_pending[2] = {};
+  int stage = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<lbm_ctx*> members;
@@ -106,6 +110,7 @@ struct BatchEngine {
                   size_t wbytes);
   // Tile used for every member instead of the members' own (-1: none).
   int tile_override = -1;
+  int row_override = -1;  // band height index for every member (-1: the member's own)
   // Uploads the members' descriptors (with `remaining` steps each, and nsub
   // sub-steps enabled before any tick) and tiles.
   lbm_status load(const std::vector<lbm_ctx*>& m, const std::vector<int64_t>& remaining,
@@ -117,8 +122,15 @@ struct BatchEngine {
   void destroy();
 };
 
-int member_tile(const lbm_ctx* c, int variant, int tile_override);
+int member_tile(const lbm_ctx* c, int variant, int tile_override, int row_override = -1);
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage);
+
+// lbm_create / lbm_init_droplets with the stream waits made optional (see
+// their definitions); the C-ABI functions call them with waits.
+lbm_status create_ctx(const lbm_params* p, void* popA, void* popB, size_t pop_bytes, void* work,
+                      size_t work_bytes, void* hip_stream, bool standalone, lbm_ctx** out);
+lbm_status init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip,
+                         bool sync);
 int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override);
 
 }  // namespace sclbm

@@ -200,11 +200,15 @@ lbm_status lbm_server::start_slot(Slot& s) {
   const WorkLayout w = work_layout(p.nx, p.ny);
   char* base = pool + s.off;
   lbm_ctx* c = nullptr;
-  lbm_status r = lbm_create(&p, base, base + pb, pb, base + 2 * pb, w.total, stream, &c);
+  // Under the continuous policy the engine drives the run, and the slot keeps
+  // the droplet list until the request completes: nothing here waits for the
+  // stream, so admissions do not drain the ticks queued ahead of the GPU.
+  const bool fifo = opts.policy == LBM_POLICY_FIFO;
+  lbm_status r = create_ctx(&p, base, base + pb, pb, base + 2 * pb, w.total, stream, fifo, &c);
   if (r != LBM_OK) return r;
   s.ctx = c;
   lbm_init ip = s.q.req.init;
-  r = lbm_init_droplets(c, s.q.drops.empty() ? nullptr : s.q.drops.data(), s.q.req.n_drops, &ip);
+  r = init_droplets(c, s.q.drops.empty() ? nullptr : s.q.drops.data(), s.q.req.n_drops, &ip, fifo);
   return r;
 }
 
@@ -470,13 +474,14 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
   // Engine workspace lives at the top of the pool.
   size_t eng_bytes = 0;
   if (!opts->fake_executor && opts->policy == LBM_POLICY_CONTINUOUS) {
-    // Strip variants: valid for every request width.
-    const int v = tile_variant(default_strip_tile(lbm_params{2048, 2048, -5.0, 1.0, 0, 0.0}));
+    // Strip variants, valid for every request width: 256-column strips suit
+    // the range of request sizes (64 .. 2048 columns) better than wider ones.
+    const int v = find_variant(256, 1, 2, 0);
     const int sw = tile_width(v * kNumRows);
     const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
                                           1u << 22);
     const int cap_items[kNumStorages] = {per, per, per};
-    const int v16 = tile_variant(default_strip_tile(lbm_params{2048, 2048, -5.0, 1.0, 1, 1.0}));
+    const int v16 = find_variant(256, 2, 1, 0);
     const int variants[kNumStorages] = {v, v16, v16};
     eng_bytes = align_up(BatchEngine::work_bytes(opts->max_slots, cap_items, opts->steps_per_tick), 256);
     if (eng_bytes >= pool_bytes / 2) {
@@ -484,6 +489,9 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
       return fail(LBM_ENOMEM, "pool too small for the batch tables");
     }
     s->eng.persistent = true;
+    // One band height for every request: the persistent grid hands items out
+    // round-robin, which balances only items of similar size.
+    s->eng.row_override = row_choice(8);
     lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, cap_items,
                                variants, s->pool + pool_bytes - eng_bytes, eng_bytes);
     if (r != LBM_OK) {
