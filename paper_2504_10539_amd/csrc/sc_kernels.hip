@@ -664,24 +664,24 @@ struct PairStrip {
       fa[7] = mix_hi(qp, kW2, w[7]);
       fb[7] = mix_lo(nqp, kW2, lane_from_next(w[7]));
     } else {
-    fa[0] = IO::lo(w[0], sh[0]);
-    fb[0] = IO::hi(w[0], sh[0]);
-    fa[2] = IO::lo(w[2], sh[2]);
-    fb[2] = IO::hi(w[2], sh[2]);
-    fa[4] = IO::lo(w[4], sh[4]);
-    fb[4] = IO::hi(w[4], sh[4]);
-    fa[1] = IO::hi_of_prev(w[1], sh[1]);
-    fb[1] = IO::lo(w[1], sh[1]);
-    fa[5] = IO::hi_of_prev(w[5], sh[5]);
-    fb[5] = IO::lo(w[5], sh[5]);
-    fa[8] = IO::hi_of_prev(w[8], sh[8]);
-    fb[8] = IO::lo(w[8], sh[8]);
-    fa[3] = IO::hi(w[3], sh[3]);
-    fb[3] = IO::lo_of_next(w[3], sh[3]);
-    fa[6] = IO::hi(w[6], sh[6]);
-    fb[6] = IO::lo_of_next(w[6], sh[6]);
-    fa[7] = IO::hi(w[7], sh[7]);
-    fb[7] = IO::lo_of_next(w[7], sh[7]);
+      fa[0] = IO::lo(w[0], sh[0]);
+      fb[0] = IO::hi(w[0], sh[0]);
+      fa[2] = IO::lo(w[2], sh[2]);
+      fb[2] = IO::hi(w[2], sh[2]);
+      fa[4] = IO::lo(w[4], sh[4]);
+      fb[4] = IO::hi(w[4], sh[4]);
+      fa[1] = IO::hi_of_prev(w[1], sh[1]);
+      fb[1] = IO::lo(w[1], sh[1]);
+      fa[5] = IO::hi_of_prev(w[5], sh[5]);
+      fb[5] = IO::lo(w[5], sh[5]);
+      fa[8] = IO::hi_of_prev(w[8], sh[8]);
+      fb[8] = IO::lo(w[8], sh[8]);
+      fa[3] = IO::hi(w[3], sh[3]);
+      fb[3] = IO::lo_of_next(w[3], sh[3]);
+      fa[6] = IO::hi(w[6], sh[6]);
+      fb[6] = IO::lo_of_next(w[6], sh[6]);
+      fa[7] = IO::hi(w[7], sh[7]);
+      fb[7] = IO::lo_of_next(w[7], sh[7]);
     }
     ps.rho_a = density(fa);
     ps.rho_b = density(fb);

@@ -64,6 +64,17 @@ def test_many_droplets_4096_fp16_windows():
     assert max(errs) < 2e-3
 
 
+def test_many_droplets_4096_fp16_cell_windows():
+    """Bench workload with FP16 storage shifted per cell (default tile)."""
+    n, G, tau = 4096, -5.5, 1.0
+    drops = inputs.many_droplets(n, 2000, 8, 48, seed=3)
+    sim = lbm().Simulation(n, n, G, tau, lbm().LBM_F16_CELL).init_droplets(drops, seed=3)
+    sim.step(K)
+    errs = _windows(sim.get_state(), n, drops, G, tau, 3, 3, 13)
+    print("4096 fp16 cell-shifted window errors", errs)
+    assert max(errs) < 2e-4
+
+
 def test_single_droplet_1024_fp32_windows():
     """1024^2, R = 200 droplet, G -5.0, tau 1.0 (windows straddle the interface)."""
     n, G, tau = 1024, -5.0, 1.0
