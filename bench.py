@@ -254,7 +254,7 @@ def run_sweep(args, torch, lbm, inputs):
             s.init_droplets(inputs.single_droplet(256, 40), seed=k)
             sims.append(s)
         batch = lbm.Batch(sims, steps_per_graph=args.graph_steps)
-        tile = batch.autotune(reps=2) if not args.no_autotune else -1
+        tile = batch.autotune(reps=5) if not args.no_autotune else -1
         batch.step(args.graph_steps)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

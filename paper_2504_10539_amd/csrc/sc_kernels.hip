@@ -346,26 +346,16 @@ __device__ __forceinline__ void march(St& s, float (*ring)[St::SW + 2],
   }
 }
 
-// Work distribution: with grab == nullptr workgroup b takes items b, b + grid,
-// ...; otherwise each workgroup takes the next item from the counter *grab
-// (zeroed before the launch) until the table is exhausted, which balances
-// persistent grids over items of unequal cost.
+// Work distribution: workgroup b takes items b, b + grid, ... of the table
+// (one item each when the grid is as large as the table).
 template <class S, int NT, int CPT, int PF>
 __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
                                              const TileItem* __restrict__ items,
-                                             const int* __restrict__ nitems_p, int sub,
-                                             int* __restrict__ grab) {
+                                             const int* __restrict__ nitems_p, int sub) {
   using St = Strip<S, NT, CPT>;
   __shared__ float ring[4][St::SW + 2];
-  __shared__ int next_item;
   const int nitems = *nitems_p;
-  int it = blockIdx.x;
-  if (grab) {
-    if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
-    __syncthreads();
-    it = next_item;
-  }
-  for (; it < nitems;) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
     if (sub < dp->nsub) {
@@ -373,14 +363,7 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
       s.setup(dp, ti, sub);
       march<St, PF>(s, ring);
     }
-    __syncthreads();  // the next item reuses the ring (and next_item)
-    if (grab) {
-      if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
-      __syncthreads();
-      it = next_item;
-    } else {
-      it += gridDim.x;
-    }
+    __syncthreads();  // the next item reuses the ring
   }
 }
 
@@ -729,20 +712,12 @@ struct PairStrip {
 template <class S, int NW, int PF>
 __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restrict__ descs,
                                                        const TileItem* __restrict__ items,
-                                                       const int* __restrict__ nitems_p, int sub,
-                                                       int* __restrict__ grab) {
+                                                       const int* __restrict__ nitems_p, int sub) {
   using St = PairStrip<S>;
   using W = typename St::W;
-  __shared__ int next_item;
   const int nitems = *nitems_p;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  int it = blockIdx.x;
-  if (grab) {
-    if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
-    __syncthreads();
-    it = next_item;
-  }
-  for (; it < nitems;) {
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
     if (sub < dp->nsub && ti.x0 + wave * kPairOut < dp->nx) {
@@ -785,24 +760,14 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
         if (pos(fa1, fb1, fa0, fb0, w0, w1, p2, p0, p1)) break;
       }
     }
-    if (grab) {
-      __syncthreads();
-      if (threadIdx.x == 0) next_item = atomicAdd(grab, 1);
-      __syncthreads();
-      it = next_item;
-    } else {
-      it += gridDim.x;
-    }
   }
 }
 
 // ============================================================== batched ticks
 
-// Start of a graph replay: every simulation takes min(K, remaining) steps,
-// and the work counters of the replay's step launches start at zero.
-__global__ void k_tick_begin(InstDesc* descs, int n, int K, int* counters, int ncounters) {
+// Start of a graph replay: every simulation takes min(K, remaining) steps.
+__global__ void k_tick_begin(InstDesc* descs, int n, int K) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < ncounters) counters[i] = 0;
   if (i < n) {
     const int64_t rem = descs[i].remaining;
     descs[i].nsub = (int32_t)(rem < K ? (rem > 0 ? rem : 0) : K);
@@ -1207,7 +1172,7 @@ template <class S, int NT, int CPT, int PF>
 hipError_t launch_step_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                          int grid, int sub, hipStream_t st) {
   hipLaunchKernelGGL((k_step<S, NT, CPT, PF>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
-                     sub, (int*)nullptr);
+                     sub);
   return hipGetLastError();
 }
 
@@ -1220,7 +1185,7 @@ template <class S, int NW, int PF>
 hipError_t launch_pair_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                          int grid, int sub, hipStream_t st) {
   hipLaunchKernelGGL((k_step_pair<S, NW, PF>), dim3(grid), dim3(64 * NW), 0, st, descs, items,
-                     nitems, sub, (int*)nullptr);
+                     nitems, sub);
   return hipGetLastError();
 }
 
@@ -1312,8 +1277,8 @@ hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t s
 
 hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t nd,
                           int storage, int variant, const InstDesc* descs, const TileItem* items,
-                          const int* nitems, int grid, int sub, int* grab) {
-  void* args[] = {(void*)&descs, (void*)&items, (void*)&nitems, (void*)&sub, (void*)&grab};
+                          const int* nitems, int grid, int sub) {
+  void* args[] = {(void*)&descs, (void*)&items, (void*)&nitems, (void*)&sub};
   hipKernelNodeParams kp{};
   kp.func = const_cast<void*>(step_fn(storage, variant));
   kp.gridDim = dim3(grid);
@@ -1325,13 +1290,12 @@ hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
 }
 
 hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps,
-                          size_t nd, bool begin, InstDesc* descs, int n, int K, int* counters,
-                          int ncounters) {
+                          size_t nd, bool begin, InstDesc* descs, int n, int K) {
   hipKernelNodeParams kp{};
-  void* args_b[] = {(void*)&descs, (void*)&n, (void*)&K, (void*)&counters, (void*)&ncounters};
+  void* args_b[] = {(void*)&descs, (void*)&n, (void*)&K};
   void* args_e[] = {(void*)&descs, (void*)&n};
   kp.func = begin ? reinterpret_cast<void*>(&k_tick_begin) : reinterpret_cast<void*>(&k_tick_end);
-  kp.gridDim = dim3((std::max(n, ncounters) + 255) / 256);
+  kp.gridDim = dim3((n + 255) / 256);
   kp.blockDim = dim3(256);
   kp.sharedMemBytes = 0;
   kp.kernelParams = begin ? args_b : args_e;

@@ -47,7 +47,7 @@ struct InitArgs {
 
 const StepVariant& step_variant(int v);
 
-// One step launch; grab == nullptr (static assignment of items to workgroups).
+// One step launch: workgroup b takes items b, b + grid, ...
 hipError_t launch_step(int storage, int variant, const InstDesc* descs, const TileItem* items,
                        const int* nitems, int grid, int sub, hipStream_t st);
 hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu);

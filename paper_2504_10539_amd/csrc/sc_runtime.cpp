@@ -382,15 +382,13 @@ lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int3
 namespace sclbm {
 hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps, size_t nd,
                           int storage, int variant, const InstDesc* descs, const TileItem* items,
-                          const int* nitems, int grid, int sub, int* grab);
+                          const int* nitems, int grid, int sub);
 hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode_t* deps,
-                          size_t nd, bool begin, InstDesc* descs, int n, int K, int* counters,
-                          int ncounters);
+                          size_t nd, bool begin, InstDesc* descs, int n, int K);
 hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t st);
 
 size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[kNumStorages], int K) {
   size_t o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
-  o += align_up((size_t)kNumStorages * K * sizeof(int), 256);  // work counters
   for (int s = 0; s < kNumStorages; ++s)
     o += 256 + align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
   return o;
@@ -407,8 +405,6 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   size_t o = 0;
   d_desc = reinterpret_cast<InstDesc*>(w);
   o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
-  d_counters = reinterpret_cast<int*>(w + o);
-  o += align_up((size_t)kNumStorages * K * sizeof(int), 256);
   const int cus = device_cu_count();
   for (int s = 0; s < kNumStorages; ++s) {
     cap_items[s] = cap_items_[s];
@@ -441,19 +437,17 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   // Graph: tick_begin -> K x (one persistent step launch per storage type) -> tick_end.
   SCLBM_HIP(hipGraphCreate(&graph, 0));
   hipGraphNode_t prev;
-  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K, d_counters,
-                           kNumStorages * K));
+  SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K));
   for (int j = 0; j < K; ++j)
     for (int s = 0; s < kNumStorages; ++s) {
       if (grid[s] == 0) continue;
       hipGraphNode_t node;
       SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, variant[s], d_desc, d_items[s],
-                               d_nitems[s], grid[s], j,
-                               dynamic ? d_counters + kNumStorages * j + s : nullptr));
+                               d_nitems[s], grid[s], j));
       prev = node;
     }
   hipGraphNode_t last;
-  SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K, nullptr, 0));
+  SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K));
   SCLBM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
   return LBM_OK;
 }

@@ -85,13 +85,9 @@ struct BatchEngine {
   int cap_items[kNumStorages] = {}, variant[kNumStorages] = {-1, -1, -1},
       grid[kNumStorages] = {}, nitems[kNumStorages] = {};
   InstDesc* d_desc = nullptr;
-  int* d_counters = nullptr;  // 2 K work counters, zeroed by the tick-begin kernel
   // Grid sized to the resident capacity, looping over the items (needed when
   // the item count changes between replays), instead of one workgroup per item.
   bool persistent = false;
-  // Items taken from the work counters instead of the static order that keeps
-  // neighbouring bands on one XCD.
-  bool dynamic = false;
   int* d_nitems[kNumStorages] = {};
   TileItem* d_items[kNumStorages] = {};
   // pinned staging of the tables, two sets used in turn (stage = next set)
