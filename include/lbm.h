@@ -149,8 +149,9 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
 lbm_status lbm_init_droplets(lbm_ctx* ctx, const double* drops, int32_t n, const lbm_init* ip);
 
 /* Enqueues n >= 0 time steps (Eq. (1)): one fused pull-stream, force and
- * collide kernel launch per step, alternating the two buffers.  Returns after
- * enqueue.  LBM_EBUSY if the context belongs to a live batch. */
+ * collide kernel launch per step (per two steps with a two-step tile shape,
+ * plus one single-step launch when n is odd), alternating the two buffers.
+ * Returns after enqueue.  LBM_EBUSY if the context belongs to a live batch. */
 lbm_status lbm_step_n(lbm_ctx* ctx, int64_t n);
 
 /* Advances n >= 0 steps like lbm_step_n and records the interface metrics of
@@ -201,18 +202,21 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * row.  paired = 0: the psi halo of a row is shared through LDS (any grid
  * width).  paired = 1: each lane holds two adjacent cells and takes its
  * column neighbours from the adjacent lanes of its wavefront; such shapes
- * need an even nx >= 128 (lbm_set_tile returns LBM_EINVAL otherwise).  Every
- * shape computes bitwise the same result; only speed differs.  Any output
- * pointer may be NULL; k out of range is LBM_EINVAL. */
+ * need an even nx >= 128 (lbm_set_tile returns LBM_EINVAL otherwise).
+ * steps = 2: one launch advances the strip two time steps, the intermediate
+ * populations kept on chip (rounded to the storage type as a store would
+ * round them); batches and servers use steps = 1 shapes only.  Every shape
+ * computes bitwise the same result; only speed differs.  Any output pointer
+ * may be NULL; k out of range is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
-                             int32_t* prefetch, int32_t* cells, int32_t* paired);
+                             int32_t* prefetch, int32_t* cells, int32_t* paired, int32_t* steps);
 lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t k);
 int32_t lbm_get_tile(const lbm_ctx* ctx);
 
 /* Times every tile shape on this run's grid (each shape `reps` launches,
  * reading the current buffer and writing the idle one, so the state is not
- * changed), selects the fastest, and records it in the tuning cache
+ * changed), selects the fastest per time step, and records it in the tuning cache
  * (a JSON file named by the SCLBM_TUNE_CACHE environment variable; no file
  * if unset) keyed by device architecture, storage and grid size.
  * Synchronises.  *best (may be NULL) receives the chosen shape. */

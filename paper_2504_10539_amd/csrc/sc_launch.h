@@ -12,11 +12,14 @@ namespace sclbm {
 // Step-kernel variants: NT threads per workgroup, CPT cells per thread, PF
 // rows of loads in flight.  Marching-strip variants (paired = 0) cover
 // NT * CPT columns per workgroup; paired-column variants (paired = 1, CPT = 2)
-// cover kPairColumns per wavefront and need an even nx >= 128.
+// cover kPairColumns per wavefront and need an even nx >= 128.  Two-step
+// variants (steps = 2, CPT = 1) advance NT - kFusedHalo columns by two time
+// steps per launch.
 struct StepVariant {
-  int threads, cells, prefetch, paired;
+  int threads, cells, prefetch, paired, steps;
 };
-constexpr int kNumVariants = 20;
+constexpr int kNumVariants = 25;
+constexpr int kFusedHalo = 6;
 constexpr int kPairColumns = 124;
 constexpr int kPairMinNx = 128;
 // Band heights a tile shape may use; tile shape k = variant * kNumRows + row

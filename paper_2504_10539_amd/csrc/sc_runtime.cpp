@@ -324,25 +324,55 @@ lbm_metrics lbm_ctx::metrics_from_raw(const double* r, int64_t step) const {
   return m;
 }
 
+// The series tile table (built on first use): strips of kSeriesThreads x 1
+// cell, 2 rows in flight, 8-row bands.  Also the single-step tile of runs
+// whose own tile takes two steps per launch.
+lbm_status lbm_ctx::series_tiles() {
+  if (series_nitems > 0) return LBM_OK;
+  const int k = find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + 0;
+  std::vector<TileItem> items;
+  make_items(p.nx, p.ny, k, 0, items);
+  items = xcd_order(items);
+  if ((int)items.size() > lay.series_items) return fail(LBM_EINVAL, "series tile table overflow");
+  const int ni = (int)items.size();
+  SCLBM_HIP(hipMemcpyAsync(d_sitems, items.data(), items.size() * sizeof(TileItem),
+                           hipMemcpyHostToDevice, stream));
+  SCLBM_HIP(hipMemcpyAsync(d_snitems, &ni, sizeof(int), hipMemcpyHostToDevice, stream));
+  SCLBM_HIP(hipStreamSynchronize(stream));
+  series_nitems = ni;
+  return LBM_OK;
+}
+
+lbm_status lbm_ctx::advance(int64_t n) {
+  const int v = tile_variant(tile);
+  const int per = tile_steps(tile);
+  for (; n >= per; n -= per) {
+    SCLBM_HIP(launch_step(p.storage, v, d_desc, d_items, d_nitems, nitems, parity, stream));
+    parity ^= 1;
+    steps += per;
+  }
+  if (n > 0) {
+    const lbm_status s = series_tiles();
+    if (s != LBM_OK) return s;
+    const int sv = find_variant(kSeriesThreads, 1, 2, 0);
+    for (; n > 0; --n) {
+      SCLBM_HIP(launch_step(p.storage, sv, d_desc, d_sitems, d_snitems, series_nitems, parity,
+                            stream));
+      parity ^= 1;
+      steps += 1;
+    }
+  }
+  return LBM_OK;
+}
+
 lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int32_t* count) {
-  if (series_nitems == 0) {
-    // strip tile of kSeriesThreads x 1 cell, 2 rows in flight, 8-row bands
-    const int k = find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + 0;
-    std::vector<TileItem> items;
-    make_items(p.nx, p.ny, k, 0, items);
-    items = xcd_order(items);
-    if ((int)items.size() > lay.series_items) return fail(LBM_EINVAL, "series tile table overflow");
-    const int ni = (int)items.size();
-    SCLBM_HIP(hipMemcpyAsync(d_sitems, items.data(), items.size() * sizeof(TileItem),
-                             hipMemcpyHostToDevice, stream));
-    SCLBM_HIP(hipMemcpyAsync(d_snitems, &ni, sizeof(int), hipMemcpyHostToDevice, stream));
-    SCLBM_HIP(hipStreamSynchronize(stream));
-    series_nitems = ni;
+  {
+    const lbm_status s = series_tiles();
+    if (s != LBM_OK) return s;
   }
   if (!h_series)
     SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_series),
                             (size_t)kSeriesChunk * 16 * sizeof(double), hipHostMallocDefault));
-  const int v = tile_variant(tile);
   int32_t done = 0, pending = 0;
   int64_t first_step = steps;
   auto flush = [&]() -> lbm_status {
@@ -357,19 +387,20 @@ lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int3
     pending = 0;
     return LBM_OK;
   };
-  for (int64_t j = 0; j < n; ++j) {
-    if (j % every == 0) {
-      SCLBM_HIP(launch_step_diag(p.storage, d_desc, d_sitems, d_snitems, series_nitems, parity,
-                                 d_spartials, d_srecords + (size_t)pending * 16, stream));
-      if (++pending == kSeriesChunk) {
-        const lbm_status s = flush();
-        if (s != LBM_OK) return s;
-      }
-    } else {
-      SCLBM_HIP(launch_step(p.storage, v, d_desc, d_items, d_nitems, nitems, parity, stream));
-    }
+  for (int64_t j = 0; j < n;) {
+    // one step that records the metrics, then the plain steps up to the next
+    SCLBM_HIP(launch_step_diag(p.storage, d_desc, d_sitems, d_snitems, series_nitems, parity,
+                               d_spartials, d_srecords + (size_t)pending * 16, stream));
     parity ^= 1;
     steps += 1;
+    if (++pending == kSeriesChunk) {
+      const lbm_status s = flush();
+      if (s != LBM_OK) return s;
+    }
+    const int64_t plain = std::min<int64_t>(every - 1, n - j - 1);
+    const lbm_status s = advance(plain);
+    if (s != LBM_OK) return s;
+    j += 1 + plain;
   }
   const lbm_status s = flush();
   if (s != LBM_OK) return s;
@@ -544,7 +575,8 @@ int member_tile(const lbm_ctx* c, int variant, int tile_override, int row_overri
 
 // Strip variant used for one storage type: that of the widest member's tile.
 // A paired-column variant is kept only if every member of that storage type
-// can run it; otherwise the widest member's default strip variant is used.
+// can run it, and a two-step variant never; otherwise the widest member's
+// default strip variant is used.
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   int best = -1, bestn = -1;
   const lbm_ctx* widest = nullptr;
@@ -556,7 +588,7 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
     }
   if (best < 0) return best;
   for (lbm_ctx* c : m)
-    if (c->p.storage == storage && !tile_valid(best * kNumRows, c->p.nx))
+    if (c->p.storage == storage && !tile_batchable(best * kNumRows, c->p.nx))
       return tile_variant(default_strip_tile(widest->p));
   return best;
 }
@@ -618,7 +650,7 @@ BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) {
   BatchShape b = batch_shape(m);
   for (int k = 0; k < kNumTiles; ++k) {
     bool valid = true;
-    for (lbm_ctx* c : m) valid = valid && tile_valid(k, c->p.nx);
+    for (lbm_ctx* c : m) valid = valid && tile_batchable(k, c->p.nx);
     if (!valid) continue;
     const BatchShape t = batch_shape(m, k);
     for (int s = 0; s < kNumStorages; ++s) b.items[s] = std::max(b.items[s], t.items[s]);
@@ -781,14 +813,7 @@ lbm_status lbm_step_n(lbm_ctx* c, int64_t n) {
   if (!c) return fail(LBM_EINVAL, "ctx is NULL");
   if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-  const int v = tile_variant(c->tile);
-  for (int64_t j = 0; j < n; ++j) {
-    SCLBM_HIP(launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
-                          c->parity, c->stream));
-    c->parity ^= 1;
-    c->steps += 1;
-  }
-  return LBM_OK;
+  return c->advance(n);
 }
 
 lbm_status lbm_step_series(lbm_ctx* c, int64_t n, int32_t every, lbm_metrics* out,
@@ -837,7 +862,7 @@ int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
 int32_t lbm_tile_count(void) { return kNumTiles; }
 
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
-                             int32_t* prefetch, int32_t* cells, int32_t* paired) {
+                             int32_t* prefetch, int32_t* cells, int32_t* paired, int32_t* steps) {
   if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
   const StepVariant& v = step_variant(tile_variant(k));
   if (width) *width = tile_width(k);
@@ -846,6 +871,7 @@ lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* 
   if (prefetch) *prefetch = v.prefetch;
   if (cells) *cells = v.cells;
   if (paired) *paired = v.paired;
+  if (steps) *steps = v.steps;
   return LBM_OK;
 }
 
@@ -890,7 +916,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
       st = hip_fail(e, "autotune launch");
       break;
     }
-    const double per = ms / reps;
+    const double per = ms / reps / tile_steps(k);  // per time step
     if (per < best_ms) {
       best_ms = per;
       best = k;
@@ -980,7 +1006,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
   lbm_status st = LBM_OK;
   for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
     bool valid = true;
-    for (lbm_ctx* c : b->members) valid = valid && tile_valid(k, c->p.nx);
+    for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx);
     if (!valid) continue;
     // Every member takes one step per launch from its current buffer into its
     // idle one and the descriptors are not advanced: the state is unchanged.

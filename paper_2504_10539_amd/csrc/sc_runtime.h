@@ -31,8 +31,11 @@ inline int tile_variant(int k) { return k / kNumRows; }
 inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }
 inline int tile_width(int k) {
   const StepVariant& v = step_variant(tile_variant(k));
+  if (v.steps == 2) return v.threads - kFusedHalo;
   return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
 }
+// Time steps one launch of tile shape k takes.
+inline int tile_steps(int k) { return step_variant(tile_variant(k)).steps; }
 // Index of the step variant with these parameters (-1 if there is none).
 inline int find_variant(int threads, int cells, int prefetch, int paired) {
   for (int v = 0; v < kNumVariants; ++v) {
@@ -47,6 +50,8 @@ inline bool tile_valid(int k, int nx) {
   const StepVariant& v = step_variant(tile_variant(k));
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
+// Whether a batch can use tile shape k (batches take one step per launch).
+inline bool tile_batchable(int k, int nx) { return tile_valid(k, nx) && tile_steps(k) == 1; }
 
 // Work items of one grid for tile shape k, appended for simulation `inst`.
 void make_items(int nx, int ny, int tile, int inst, std::vector<TileItem>& out);
@@ -160,6 +165,10 @@ struct lbm_ctx {
 
   sclbm::InstDesc host_desc() const;
   lbm_status upload_tile(int k);
+  lbm_status series_tiles();
+  // n steps with the run's tile (two-step tiles: pairs, and one single step
+  // with the series strip tile if n is odd).
+  lbm_status advance(int64_t n);
   lbm_status diagnostics(lbm_metrics* out);
   lbm_status step_series(int64_t n, int32_t every, lbm_metrics* out, int32_t* count);
   lbm_metrics metrics_from_raw(const double* r, int64_t step) const;

@@ -118,7 +118,7 @@ _PROTOS = {
     "lbm_step_count": (_i64, [_vp]),
     "lbm_tile_count": (_i32, []),
     "lbm_tile_describe": (_i32, [_i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32),
-                                 _P(_i32)]),
+                                 _P(_i32), _P(_i32)]),
     "lbm_set_tile": (_i32, [_vp, _i32]),
     "lbm_get_tile": (_i32, [_vp]),
     "lbm_autotune": (_i32, [_vp, _i32, _P(_i32)]),
@@ -237,12 +237,14 @@ def carve(pool, sizes):
 def tiles() -> list[dict]:
     out = []
     for k in range(LIB.lbm_tile_count()):
-        w, r, t, p, c, pa = _i32(), _i32(), _i32(), _i32(), _i32(), _i32()
+        w, r, t, p, c, pa, st = _i32(), _i32(), _i32(), _i32(), _i32(), _i32(), _i32()
         _check(LIB.lbm_tile_describe(k, ctypes.byref(w), ctypes.byref(r), ctypes.byref(t),
-                                     ctypes.byref(p), ctypes.byref(c), ctypes.byref(pa)),
+                                     ctypes.byref(p), ctypes.byref(c), ctypes.byref(pa),
+                                     ctypes.byref(st)),
                "lbm_tile_describe")
         out.append({"id": k, "width": w.value, "rows": r.value, "threads": t.value,
-                    "prefetch": p.value, "cells": c.value, "paired": pa.value})
+                    "prefetch": p.value, "cells": c.value, "paired": pa.value,
+                    "steps": st.value})
     return out
 
 

@@ -108,9 +108,13 @@ def test_tile_table(lbm):
     assert len({(t["width"], t["rows"], t["threads"], t["prefetch"]) for t in tiles}) == len(tiles)
     w = ctypes.c_int32()
     assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None, None,
-                                     None) == lbm.LBM_EINVAL
+                                     None, None) == lbm.LBM_EINVAL
     for t in tiles:
-        if t["paired"]:
+        assert t["steps"] in (1, 2)
+        if t["steps"] == 2:  # three halo columns on each side of the strip
+            assert not t["paired"] and t["cells"] == 1 and t["width"] == t["threads"] - 6
+        elif t["paired"]:
             assert t["cells"] == 2 and t["width"] == t["threads"] // 64 * 124
         else:
             assert t["width"] == t["threads"] * t["cells"]
+    assert any(t["steps"] == 2 for t in tiles)

@@ -27,6 +27,21 @@ def test_kernel_names(lbm):
         f"k_step<StoreF32, 512, 1, {strip['prefetch']}>"
     assert bench.kernel_name(lbm, pair["id"], lbm.LBM_F16_SHIFTED) == \
         f"k_step_pair<StoreF16S, 4, {pair['prefetch']}>"
+    two = next(t for t in tiles if t["steps"] == 2 and t["threads"] == 256)
+    assert bench.kernel_name(lbm, two["id"], lbm.LBM_F16_CELL) == \
+        f"k_step2<StoreF16C, 256, {two['prefetch']}>"
+
+
+def test_launch_figures_count_one_read_and_write_per_launch(lbm):
+    tiles = lbm.tiles()
+    one = next(t for t in tiles if t["steps"] == 1)
+    two = next(t for t in tiles if t["steps"] == 2)
+    a = bench.launch_figures(lbm, one["id"], 0.1, 72, 1000)
+    b = bench.launch_figures(lbm, two["id"], 0.1, 72, 1000)
+    assert a["steps_per_launch"] == 1 and b["steps_per_launch"] == 2
+    assert a["launch_ms"] == pytest.approx(0.1) and b["launch_ms"] == pytest.approx(0.2)
+    assert a["achieved_gbs"] == pytest.approx(72 * 1000 / 1e-4 / 1e9)
+    assert b["achieved_gbs"] == pytest.approx(a["achieved_gbs"] / 2)
 
 
 def test_traffic_lookup_requires_matching_sources(lbm, tmp_path, monkeypatch):

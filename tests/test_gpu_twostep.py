@@ -1,0 +1,131 @@
+"""Two-step tile shapes: one launch advances its strip by two time steps, the
+intermediate post-collision populations kept on chip and rounded to the
+storage type exactly as a store and a reload would round them.
+
+Bar: every two-step shape reproduces the single-step path bitwise (every
+storage type, ragged and degenerate grids, odd step counts split over calls),
+and the FP64 oracle to FP32 rounding; the fused metric series and batches are
+unchanged by a run's two-step tile.  Method: Li & Zhang, arXiv 2504.10539,
+Sec. II-A Eq. (1).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_10539_amd import inputs
+from tests.gpu_helpers import f32_state, lbm, need_gpu, set_state_from, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _two_step(rows=None):
+    return [t for t in lbm().tiles() if t["steps"] == 2 and (rows is None or t["rows"] in rows)]
+
+
+def _strip_tile():
+    return next(t["id"] for t in lbm().tiles() if t["steps"] == 1 and not t["paired"]
+                and t["threads"] == 256 and t["cells"] == 1 and t["prefetch"] == 2
+                and t["rows"] == 8)
+
+
+def _rho0(storage):
+    return 1.0 if storage == lbm().LBM_F16_SHIFTED else 0.0
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (5, 3), (40, 9), (250, 2), (251, 13), (300, 77),
+                                   (513, 5)])
+def test_two_step_shapes_match_single_step(storage, nx, ny):
+    """Strips narrower than the halo, one-row and short last bands, widths
+    around the strip width; 7 steps as 1 + 6 (one single-step launch, then
+    three two-step launches)."""
+    L = lbm()
+    f0 = f32_state(inputs.random_positive_state(nx, ny, seed=nx * 7 + ny))
+    ref = L.Simulation(nx, ny, -5.5, 0.8, storage, _rho0(storage))
+    ref.set_tile(_strip_tile())
+    set_state_from(ref, f0)
+    ref.step(7)
+    want = to_np(ref.get_state())
+    for t in _two_step(rows=(2, 8, 128)):
+        s = L.Simulation(nx, ny, -5.5, 0.8, storage, _rho0(storage))
+        s.set_tile(t["id"])
+        set_state_from(s, f0)
+        s.step(1)
+        s.step(6)
+        assert s.steps == 7
+        got = to_np(s.get_state())
+        assert np.array_equal(got, want), (t, nx, ny, storage)
+        s.close()
+
+
+def test_two_step_matches_oracle():
+    nx, ny, G, tau = 96, 70, -5.5, 0.8
+    f0 = f32_state(inputs.random_positive_state(nx, ny, seed=3))
+    for t in _two_step(rows=(8,)):
+        s = lbm().Simulation(nx, ny, G, tau)
+        s.set_tile(t["id"])
+        set_state_from(s, f0)
+        s.step(4)
+        got = to_np(s.get_state())
+        ref = oracle.step(f0, G, tau, 4)
+        assert float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))) < 8e-6, t
+
+
+def test_droplet_run_with_two_step_tile_meets_oracle_bar():
+    """64^2 droplet, 1000 steps, density within 1e-5 of the oracle (Sec. III-A)."""
+    N, G, tau = 64, -5.0, 1.0
+    drops = inputs.single_droplet(N, 16)
+    s = lbm().Simulation(N, N, G, tau).init_droplets(drops, seed=1)
+    s.set_tile(_two_step(rows=(8,))[0]["id"])
+    s.step(1000)
+    rho = to_np(s.moments()[0])
+    ref = oracle.density(oracle.step(oracle.droplet_state(N, N, drops, seed=1), G, tau, 1000, 8))
+    assert float(np.max(np.abs(rho - ref) / ref)) < 1e-5
+
+
+@pytest.mark.parametrize("storage", [0, 2])
+def test_series_with_two_step_tile_is_unchanged(storage):
+    """step_series runs its recording steps with the series strip tile and the
+    steps between them with the run's tile: records and final state equal
+    those of a single-step run."""
+    L = lbm()
+    nx, ny = 200, 90
+    drops = [(80.0, 45.0, 20.0), (170.0, 20.0, 9.0)]
+    runs = []
+    for tile in (_strip_tile(), _two_step(rows=(8,))[1]["id"]):
+        s = L.Simulation(nx, ny, -5.5, 1.0, storage, _rho0(storage)).init_droplets(drops, seed=2)
+        s.set_tile(tile)
+        recs = s.step_series(25, 4)
+        runs.append((recs, to_np(s.get_state()), s.steps))
+    (ra, sa, na), (rb, sb, nb) = runs
+    assert na == nb == 25
+    assert np.array_equal(sa, sb)
+    assert len(ra) == len(rb) == 7
+    for a, b in zip(ra, rb):
+        assert a == b
+
+
+def test_batch_member_with_two_step_tile():
+    """Batches take one step per launch: a member whose own tile takes two runs
+    with a single-step shape inside the batch, bitwise as alone."""
+    L = lbm()
+    mk = [lambda: L.Simulation(120, 64, -5.0, 1.0).init_droplets([(50, 30, 14)], seed=5),
+          lambda: L.Simulation(96, 96, -5.5, 0.9, L.LBM_F16_CELL).init_droplets([(40, 40, 15)], seed=6)]
+    two = _two_step(rows=(8,))[0]["id"]
+    batch = [m() for m in mk]
+    solo = [m() for m in mk]
+    for s in batch + solo:
+        s.set_tile(two)
+    bt = L.Batch(batch, steps_per_graph=8)
+    bt.step(13)
+    for s in solo:
+        s.step(13)
+    for a, s in zip(batch, solo):
+        assert a.steps == s.steps == 13
+        assert np.array_equal(to_np(a.get_state()), to_np(s.get_state()))
+    bt.close()
