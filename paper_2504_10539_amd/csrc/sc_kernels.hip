@@ -401,337 +401,6 @@ __global__ __launch_bounds__(kDiagThreads) void k_step_diag(const InstDesc* __re
   }
 }
 
-// ============================================================== two fused time steps
-//
-// Temporal blocking: a workgroup advances its strip of a band by two time
-// steps in one pass, so the populations cross HBM once per two updates.  The
-// post-collision values of the intermediate step never leave the CU: they go
-// through a four-row LDS ring, rounded through the storage form exactly as a
-// store and a load would round them, so the result is bitwise that of two
-// single steps.  Thread t owns column x0 - 3 + t (mod nx).  Per march row j:
-//   1. pull f(t) of row j + 3 (loads issued PF rows ahead), publish psi(t);
-//   2. collide row j + 2 into the ring (columns x0 - 2 .. x0 + W + 1);
-//   3. pull f(t + 1) of row j + 1 from the ring, publish psi(t + 1);
-//   4. collide row j and store it (columns x0 .. x0 + W - 1).
-// One barrier separates each stage from the next.  The band's rows are
-// reached through three halo rows above and below; W = NT - 6 columns.
-
-template <class S>
-struct RawCell {
-  typename S::T v[9];
-  typename S::T q[9];  // reference densities (per-cell-shift storage)
-};
-
-template <class S, int NT, int PF>
-struct Fused2 {
-  using T = typename S::T;
-  static constexpr int W = NT - 6;
-
-  uint64_t src, dst;
-  float sh[9];
-  int nx, ny, y0, h, dir, wcols;
-  uint32_t bc, bm, bp;  // byte offsets of this thread's column and its neighbours
-  bool out;             // this thread stores a cell of the second step
-  float G, tau, omega;
-
-  __device__ __forceinline__ static uint64_t uniform(uint64_t v) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-  }
-  __device__ __forceinline__ static uint32_t fresh(uint32_t v) {
-    asm volatile("" : "+v"(v));
-    return v;
-  }
-  template <class P>
-  __device__ __forceinline__ static P at(P base, uint32_t boff) {
-    using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
-                                        const char, char>::type;
-    return reinterpret_cast<P>(reinterpret_cast<__attribute__((address_space(1))) C*>(base) + boff);
-  }
-  __device__ __forceinline__ gptr<const T> in_row(int i, int y) const {
-    return as_global<const T>(uniform(src + row_index(i, y, nx, ny) * sizeof(T)));
-  }
-  __device__ __forceinline__ gptr<T> out_row(int i, int y) const {
-    return as_global<T>(uniform(dst + row_index(i, y, nx, ny) * sizeof(T)));
-  }
-  __device__ __forceinline__ gptr<const T> rhat_in(int y) const {
-    return as_global<const T>(uniform(src + rhat_row(y, nx, ny) * sizeof(T)));
-  }
-  __device__ __forceinline__ gptr<T> rhat_out(int y) const {
-    return as_global<T>(uniform(dst + rhat_row(y, nx, ny) * sizeof(T)));
-  }
-
-  __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti,
-                                        int sub) {
-    nx = dp->nx;
-    ny = dp->ny;
-    y0 = ti.y0;
-    h = ti.h;
-    dir = ti.dir;
-    wcols = min(W, nx - ti.x0);
-    G = dp->G;
-    tau = dp->tau;
-    omega = dp->omega;
-    const float rho0 = dp->rho0;
-    const int par = (dp->parity + sub) & 1;
-    const uint64_t a = dp->pop[0], b = dp->pop[1];
-    src = par ? b : a;
-    dst = par ? a : b;
-    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
-    const int t = threadIdx.x;
-    int c = (ti.x0 - 3 + t) % nx;
-    c = c < 0 ? c + nx : c;
-    bc = (uint32_t)c * (uint32_t)sizeof(T);
-    bm = (uint32_t)wrap_dec(c, nx) * (uint32_t)sizeof(T);
-    bp = (uint32_t)wrap_inc(c, nx) * (uint32_t)sizeof(T);
-    out = t >= 3 && t - 3 < wcols;
-  }
-
-  // Lattice row of march position j (any j in [-3, h + 2]).
-  __device__ __forceinline__ int row_of(int j) const {
-    int y = (dir ? y0 + h - 1 - j : y0 + j) % ny;
-    return y < 0 ? y + ny : y;
-  }
-
-  // Issues the loads of row j's pulled populations (f_i(x) = A_i(x - e_i))
-  // into v, and for per-cell-shift storage the reference densities of the
-  // cells they come from into q.
-  __device__ __forceinline__ void fetch(int j, T* v, T* q) const {
-    const int y = row_of(j);
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const uint32_t c = fresh(bc), m = fresh(bm), p = fresh(bp);
-    v[0] = *at(in_row(0, y), c);
-    v[1] = *at(in_row(1, y), m);
-    v[2] = *at(in_row(2, ym), c);
-    v[3] = *at(in_row(3, y), p);
-    v[4] = *at(in_row(4, yp), c);
-    v[5] = *at(in_row(5, ym), m);
-    v[6] = *at(in_row(6, ym), p);
-    v[7] = *at(in_row(7, yp), p);
-    v[8] = *at(in_row(8, yp), m);
-    if constexpr (S::kCellShift) {
-      q[0] = *at(rhat_in(y), c);
-      q[1] = *at(rhat_in(y), m);
-      q[2] = *at(rhat_in(ym), c);
-      q[3] = *at(rhat_in(y), p);
-      q[4] = *at(rhat_in(yp), c);
-      q[5] = *at(rhat_in(ym), m);
-      q[6] = *at(rhat_in(ym), p);
-      q[7] = *at(rhat_in(yp), p);
-      q[8] = *at(rhat_in(yp), m);
-    }
-  }
-
-  __device__ __forceinline__ void decode(const RawCell<S>& r, float (&f)[10]) const {
-    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      if constexpr (S::kCellShift)
-        f[i] = S::decode(r.v[i], r.q[i], ws[i]);
-      else
-        f[i] = S::load(&r.v[i], sh[i]);
-    }
-    f[9] = density(f);
-  }
-
-  // A post-collision value as the next step would read it back from storage.
-  __device__ __forceinline__ float through_storage(float v, int i, float rho) const {
-    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-    if constexpr (S::kCellShift) {
-      const T rh = S::ref(rho);
-      return S::decode(S::encode(v, rh, ws[i]), rh, ws[i]);
-    } else {
-      const T hv = S::pack(v, sh[i]);
-      return S::load(&hv, sh[i]);
-    }
-  }
-
-  // Stores of a row go through buffer resources with the row as its range:
-  // lanes that own no output column pass an offset past the end, and the
-  // hardware drops those stores.  No branch around the stores, so the wait
-  // counts before the next loads stay exact (loads issued before a
-  // branch-skipped store block would otherwise be waited for with the stores).
-  template <class V>
-  __device__ __forceinline__ void put(gptr<V> row, uint32_t off, V v) const {
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)row, (short)0, nx * (int)sizeof(V), 0x00020000);
-    if constexpr (sizeof(V) == 4)
-      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
-                                            S::kStream ? 2 : 0);  // 2: non-temporal
-    else
-      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)off, 0, 0);
-  }
-
-  __device__ __forceinline__ void store(int j, const float (&f)[10]) const {
-    const int y = row_of(j);
-    const uint32_t c = out ? fresh(bc) : 0x80000000u;
-    if constexpr (S::kCellShift) {
-      const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-      const T rh = S::ref(f[9]);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) put(out_row(i, y), c, S::encode(f[i], rh, ws[i]));
-      put(rhat_out(y), c, rh);
-    } else {
-#pragma unroll
-      for (int i = 0; i < 9; ++i) put(out_row(i, y), c, S::pack(f[i], sh[i]));
-    }
-  }
-};
-
-// Interaction force at thread t from three psi ring rows: dn holds row y - 1,
-// md row y, up row y + 1 (LDS index = thread).
-__device__ __forceinline__ void ring_force(const float* dn, const float* md, const float* up, int t,
-                                           float G, float& Fx, float& Fy) {
-  force_of(md[t], md[t + 1], up[t], md[t - 1], dn[t], up[t + 1], up[t - 1], dn[t - 1], dn[t + 1], G,
-           Fx, Fy);
-}
-
-// Ring slot of march row r >= -9 (three rows of each ring are live at a time).
-__device__ __forceinline__ int slot3(int r) { return (r + 9) % 3; }
-
-// Calls fn(integral_constant<int, I>) for I = 0, 1, ... in order.
-template <class Fn, int... I>
-__device__ __forceinline__ void unrolled(std::integer_sequence<int, I...>, Fn&& fn) {
-  (fn(std::integral_constant<int, I>{}), ...);
-}
-
-template <class S, int NT, int PF>
-__global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs,
-                                              const TileItem* __restrict__ items,
-                                              const int* __restrict__ nitems_p, int sub) {
-  static_assert(PF == 1 || PF == 2, "one or two rows of loads in flight");
-  using F = Fused2<S, NT, PF>;
-  using T = typename S::T;
-  // FP32 rows are loaded straight into the registers they are collided in:
-  // a slot lives from its loads to the first collision, PF + 2 positions.
-  // Half-precision rows land in PF + 1 raw slots and are widened into two
-  // rotating FP32 rows.  The loads of a position always go to a slot that is
-  // idle at that point.  The march is unrolled over U positions, a multiple
-  // of every rotation period, so each slot stays in fixed registers.
-  constexpr bool kInPlace = std::is_same<S, StoreF32>::value;
-  constexpr int NR = kInPlace ? PF + 2 : PF + 1;
-  // With U a multiple of 3 the LDS ring slots are constants too (not taken
-  // for per-cell-shift storage, whose longer period needs too many registers).
-  constexpr int U = ((NR == 2 && !S::kCellShift) || NR == 3) ? 6 : (NR % 2 == 0 ? NR : 2 * NR);
-  constexpr bool kFixedRing = U % 3 == 0;
-  constexpr int NF = kInPlace ? NR : 2;  // FP32 rows of the first step
-  __shared__ float psa[3][NT];    // psi(t) rows
-  __shared__ float fs[3][9][NT];  // f*(t + 1) rows, as read back from storage
-  __shared__ float psb[3][NT];    // psi(t + 1) rows
-  const int nitems = *nitems_p;
-  const int t = threadIdx.x;
-  const bool stage_a = t >= 1 && t <= NT - 2;
-  const bool stage_b = t >= 2 && t <= NT - 3;
-  // Lanes that store nothing still run the last collision (on clamped ring
-  // columns) so that the row's stores need no branch.
-  const int tf = min(max(t, 1), NT - 2);
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
-    const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
-    if (sub < dp->nsub) {
-      F s;
-      s.setup(dp, ti, sub);
-      const int h = s.h;
-      // The march is instantiated per direction, so that every ring access
-      // is the lane's LDS address plus a constant.  In march order the row
-      // below a row (y - 1) is the previous one when marching downwards and
-      // the next one when marching upwards.
-      auto march = [&](auto upward_c) {
-      constexpr int below = decltype(upward_c)::value ? 1 : -1;
-      RawCell<S> raw[kInPlace ? 1 : NR];
-      float fa[NF][10], fb[2][10];
-      // Row R (>= -3) of the first step is loaded into slot R mod NR.
-      auto fetch_row = [&](int row, auto slot_c) {
-        constexpr int k = decltype(slot_c)::value;
-        if constexpr (kInPlace)
-          s.fetch(row, fa[k], nullptr);
-        else
-          s.fetch(row, raw[k].v, raw[k].q);
-      };
-      unrolled(std::make_integer_sequence<int, PF>{}, [&](auto k) {
-        fetch_row(-3 + decltype(k)::value,
-                  std::integral_constant<int, (decltype(k)::value + 3 * NR - 3) % NR>{});
-      });
-      // March position j with phase u = j mod U: issue the loads of row
-      // j + 3 + PF (the band's last row again past its end); decode row j + 3
-      // and publish psi(t); collide row j + 2 into the ring; pull f(t + 1) of
-      // row j + 1 and publish psi(t + 1); collide row j and store it.
-      auto pos = [&](auto lead_c, auto u_c, int j) {
-        constexpr bool kLead = decltype(lead_c)::value;  // j < 0: no output row yet
-        constexpr int u = decltype(u_c)::value;
-        constexpr int kd = (u + 3) % NR;  // slot of row j + 3
-        // ring slot of row j + d (j = u mod U)
-        auto ring = [&](int d) { return kFixedRing ? (u + d + 9) % 3 : slot3(j + d); };
-        float(&fa_c)[10] = fa[kInPlace ? kd : (u + 3) & 1];
-        float(&fa_p)[10] = fa[kInPlace ? (u + 2) % NR : (u + 2) & 1];
-        float(&fb_c)[10] = fb[(u + 1) & 1];
-        float(&fb_p)[10] = fb[u & 1];
-        fetch_row(min(j + 3 + PF, h + 2), std::integral_constant<int, (u + 3 + PF) % NR>{});
-        if constexpr (kInPlace)
-          fa_c[9] = density(fa_c);
-        else
-          s.decode(raw[kd], fa_c);
-        psa[ring(3)][t] = psi_of(fa_c[9]);
-        __syncthreads();
-        if ((!kLead || j >= -4) && stage_a) {  // row j + 2
-          float Fx, Fy;
-          ring_force(psa[ring(2 + below)], psa[ring(2)], psa[ring(2 - below)], t, s.G, Fx, Fy);
-          const float rho = fa_p[9];
-          collide(fa_p, rho, Fx, Fy, s.tau, s.omega);
-#pragma unroll
-          for (int i = 0; i < 9; ++i) fs[ring(2)][i][t] = s.through_storage(fa_p[i], i, rho);
-        }
-        __syncthreads();
-        if ((!kLead || j >= -2) && stage_b) {
-          // row j + 1: f_i(x) = f*_i(x - e_i), rows below feed e_iy = +1
-          const float(*dn)[NT] = fs[ring(1 + below)];
-          const float(*md)[NT] = fs[ring(1)];
-          const float(*up)[NT] = fs[ring(1 - below)];
-          fb_c[0] = md[0][t];
-          fb_c[1] = md[1][t - 1];
-          fb_c[2] = dn[2][t];
-          fb_c[3] = md[3][t + 1];
-          fb_c[4] = up[4][t];
-          fb_c[5] = dn[5][t - 1];
-          fb_c[6] = dn[6][t + 1];
-          fb_c[7] = up[7][t + 1];
-          fb_c[8] = up[8][t - 1];
-          fb_c[9] = density(fb_c);
-          psb[ring(1)][t] = psi_of(fb_c[9]);
-        }
-        __syncthreads();
-        if constexpr (!kLead) {
-          float Fx, Fy;
-          ring_force(psb[ring(below)], psb[ring(0)], psb[ring(-below)], tf, s.G, Fx, Fy);
-          collide(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
-          s.store(j, fb_p);
-        }
-      };
-      // six lead-in positions, j = -6 .. -1
-      unrolled(std::make_integer_sequence<int, 6>{}, [&](auto k) {
-        constexpr int j = decltype(k)::value - 6;
-        pos(std::true_type{}, std::integral_constant<int, (j % U + U) % U>{}, j);
-      });
-      const auto phases = std::make_integer_sequence<int, U>{};
-      int j0 = 0;
-      for (; j0 + U <= h; j0 += U)
-        unrolled(phases, [&](auto u) { pos(std::false_type{}, u, j0 + decltype(u)::value); });
-      unrolled(std::make_integer_sequence<int, U - 1>{}, [&](auto u) {
-        if (j0 + decltype(u)::value < h) pos(std::false_type{}, u, j0 + decltype(u)::value);
-      });
-      };
-      if (s.dir)
-        march(std::true_type{});
-      else
-        march(std::false_type{});
-    }
-    __syncthreads();  // the next item reuses the rings
-  }
-}
-
 // ============================================================== paired-column step kernel
 //
 // Wave-local variant of the same step.  Each lane loads one aligned pair of
@@ -1094,6 +763,352 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
         if (pos(fa1, fb1, fa0, fb0, w0, w1, p2, p0, p1)) break;
       }
     }
+  }
+}
+
+// ============================================================== two fused time steps
+//
+// Temporal blocking: a workgroup advances its strip of a band by two time
+// steps in one pass, so the populations cross HBM once per two updates.  The
+// post-collision values of the intermediate step never leave the CU: they go
+// through a four-row LDS ring, rounded through the storage form exactly as a
+// store and a load would round them, so the result is bitwise that of two
+// single steps.  Thread t owns column x0 - 3 + t (mod nx).  Per march row j:
+//   1. pull f(t) of row j + 3 (loads issued PF rows ahead), publish psi(t);
+//   2. collide row j + 2 into the ring (columns x0 - 2 .. x0 + W + 1);
+//   3. pull f(t + 1) of row j + 1 from the ring, publish psi(t + 1);
+//   4. collide row j and store it (columns x0 .. x0 + W - 1).
+// One barrier separates each stage from the next.  The band's rows are
+// reached through three halo rows above and below; W = NT - 6 columns.
+
+template <class S>
+struct RawCell {
+  typename S::T v[9];
+  typename S::T q[9];  // reference densities (per-cell-shift storage)
+};
+
+template <class S, int NT, int PF>
+struct Fused2 {
+  using T = typename S::T;
+  static constexpr int W = NT - 6;
+
+  uint64_t src, dst;
+  float sh[9];
+  int nx, ny, y0, h, dir, wcols;
+  uint32_t bc, bm, bp;  // byte offsets of this thread's column and its neighbours
+  bool out;             // this thread stores a cell of the second step
+  float G, tau, omega;
+
+  __device__ __forceinline__ static uint64_t uniform(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+  }
+  __device__ __forceinline__ static uint32_t fresh(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
+  }
+  template <class P>
+  __device__ __forceinline__ static P at(P base, uint32_t boff) {
+    using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
+                                        const char, char>::type;
+    return reinterpret_cast<P>(reinterpret_cast<__attribute__((address_space(1))) C*>(base) + boff);
+  }
+  __device__ __forceinline__ gptr<const T> in_row(int i, int y) const {
+    return as_global<const T>(uniform(src + row_index(i, y, nx, ny) * sizeof(T)));
+  }
+  __device__ __forceinline__ gptr<T> out_row(int i, int y) const {
+    return as_global<T>(uniform(dst + row_index(i, y, nx, ny) * sizeof(T)));
+  }
+  __device__ __forceinline__ gptr<const T> rhat_in(int y) const {
+    return as_global<const T>(uniform(src + rhat_row(y, nx, ny) * sizeof(T)));
+  }
+  __device__ __forceinline__ gptr<T> rhat_out(int y) const {
+    return as_global<T>(uniform(dst + rhat_row(y, nx, ny) * sizeof(T)));
+  }
+
+  __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti,
+                                        int sub) {
+    nx = dp->nx;
+    ny = dp->ny;
+    y0 = ti.y0;
+    h = ti.h;
+    dir = ti.dir;
+    wcols = min(W, nx - ti.x0);
+    G = dp->G;
+    tau = dp->tau;
+    omega = dp->omega;
+    const float rho0 = dp->rho0;
+    const int par = (dp->parity + sub) & 1;
+    const uint64_t a = dp->pop[0], b = dp->pop[1];
+    src = par ? b : a;
+    dst = par ? a : b;
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
+    const int t = threadIdx.x;
+    int c = (ti.x0 - 3 + t) % nx;
+    c = c < 0 ? c + nx : c;
+    bc = (uint32_t)c * (uint32_t)sizeof(T);
+    bm = (uint32_t)wrap_dec(c, nx) * (uint32_t)sizeof(T);
+    bp = (uint32_t)wrap_inc(c, nx) * (uint32_t)sizeof(T);
+    out = t >= 3 && t - 3 < wcols;
+  }
+
+  // Lattice row of march position j (any j in [-3, h + 2]).
+  __device__ __forceinline__ int row_of(int j) const {
+    int y = (dir ? y0 + h - 1 - j : y0 + j) % ny;
+    return y < 0 ? y + ny : y;
+  }
+
+  // Issues the loads of row j's pulled populations (f_i(x) = A_i(x - e_i))
+  // into v, and for per-cell-shift storage the reference densities of the
+  // cells they come from into q.
+  __device__ __forceinline__ void fetch(int j, T* v, T* q) const {
+    const int y = row_of(j);
+    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+    const uint32_t c = fresh(bc), m = fresh(bm), p = fresh(bp);
+    v[0] = *at(in_row(0, y), c);
+    v[1] = *at(in_row(1, y), m);
+    v[2] = *at(in_row(2, ym), c);
+    v[3] = *at(in_row(3, y), p);
+    v[4] = *at(in_row(4, yp), c);
+    v[5] = *at(in_row(5, ym), m);
+    v[6] = *at(in_row(6, ym), p);
+    v[7] = *at(in_row(7, yp), p);
+    v[8] = *at(in_row(8, yp), m);
+    if constexpr (S::kCellShift) {
+      q[0] = *at(rhat_in(y), c);
+      q[1] = *at(rhat_in(y), m);
+      q[2] = *at(rhat_in(ym), c);
+      q[3] = *at(rhat_in(y), p);
+      q[4] = *at(rhat_in(yp), c);
+      q[5] = *at(rhat_in(ym), m);
+      q[6] = *at(rhat_in(ym), p);
+      q[7] = *at(rhat_in(yp), p);
+      q[8] = *at(rhat_in(yp), m);
+    }
+  }
+
+  // Bits of a half in the low 16 bits of a word (the mixed-precision FMAs
+  // below read only those).
+  __device__ __forceinline__ static uint32_t bits(T h) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
+  }
+
+  // Widening of the pulled values, as the storage type reads them back.  For
+  // per-cell-shift storage one mixed-precision FMA per value (rhohat * w_i + h,
+  // both halves read directly), equal to StoreF16C::decode.  (The same form
+  // for the FP16-shifted values, float(h) + w_i rho0, is also exact, but the
+  // compiler then needs some 35 more VGPRs for that kernel.)
+  __device__ __forceinline__ void decode(const RawCell<S>& r, float (&f)[10]) const {
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (S::kCellShift)
+        f[i] = mix_lo(bits(r.q[i]), ws[i], bits(r.v[i]));
+      else
+        f[i] = S::load(&r.v[i], sh[i]);
+    }
+    f[9] = density(f);
+  }
+
+  // A post-collision value as the next step would read it back from storage.
+  __device__ __forceinline__ float through_storage(float v, int i, float rho) const {
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+    if constexpr (S::kCellShift) {
+      const T rh = S::ref(rho);
+      return mix_lo(bits(rh), ws[i], bits(S::encode(v, rh, ws[i])));
+    } else if constexpr (sizeof(T) == 2) {
+      const T hv = S::pack(v, sh[i]);
+      return S::load(&hv, sh[i]);
+    } else {
+      return v;  // FP32 stores the value itself
+    }
+  }
+
+  // Stores of a row go through buffer resources with the row as its range:
+  // lanes that own no output column pass an offset past the end, and the
+  // hardware drops those stores.  No branch around the stores, so the wait
+  // counts before the next loads stay exact (loads issued before a
+  // branch-skipped store block would otherwise be waited for with the stores).
+  template <class V>
+  __device__ __forceinline__ void put(gptr<V> row, uint32_t off, V v) const {
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)row, (short)0, nx * (int)sizeof(V), 0x00020000);
+    if constexpr (sizeof(V) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
+                                            S::kStream ? 2 : 0);  // 2: non-temporal
+    else
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, (int)off, 0, 0);
+  }
+
+  __device__ __forceinline__ void store(int j, const float (&f)[10]) const {
+    const int y = row_of(j);
+    const uint32_t c = out ? fresh(bc) : 0x80000000u;
+    if constexpr (S::kCellShift) {
+      const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+      const T rh = S::ref(f[9]);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) put(out_row(i, y), c, S::encode(f[i], rh, ws[i]));
+      put(rhat_out(y), c, rh);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) put(out_row(i, y), c, S::pack(f[i], sh[i]));
+    }
+  }
+};
+
+// Interaction force at thread t from three psi ring rows: dn holds row y - 1,
+// md row y, up row y + 1 (LDS index = thread).
+__device__ __forceinline__ void ring_force(const float* dn, const float* md, const float* up, int t,
+                                           float G, float& Fx, float& Fy) {
+  force_of(md[t], md[t + 1], up[t], md[t - 1], dn[t], up[t + 1], up[t - 1], dn[t - 1], dn[t + 1], G,
+           Fx, Fy);
+}
+
+// Ring slot of march row r >= -9 (three rows of each ring are live at a time).
+__device__ __forceinline__ int slot3(int r) { return (r + 9) % 3; }
+
+// Calls fn(integral_constant<int, I>) for I = 0, 1, ... in order.
+template <class Fn, int... I>
+__device__ __forceinline__ void unrolled(std::integer_sequence<int, I...>, Fn&& fn) {
+  (fn(std::integral_constant<int, I>{}), ...);
+}
+
+template <class S, int NT, int PF>
+__global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs,
+                                              const TileItem* __restrict__ items,
+                                              const int* __restrict__ nitems_p, int sub) {
+  static_assert(PF == 1 || PF == 2, "one or two rows of loads in flight");
+  using F = Fused2<S, NT, PF>;
+  using T = typename S::T;
+  // FP32 rows are loaded straight into the registers they are collided in:
+  // a slot lives from its loads to the first collision, PF + 2 positions.
+  // Half-precision rows land in PF + 1 raw slots and are widened into two
+  // rotating FP32 rows.  The loads of a position always go to a slot that is
+  // idle at that point.  The march is unrolled over U positions, a multiple
+  // of every rotation period, so each slot stays in fixed registers.
+  constexpr bool kInPlace = std::is_same<S, StoreF32>::value;
+  constexpr int NR = kInPlace ? PF + 2 : PF + 1;
+  // With U a multiple of 3 the LDS ring slots are constants too (not taken
+  // for per-cell-shift storage, whose longer period needs too many registers).
+  constexpr int U = ((NR == 2 && !S::kCellShift) || NR == 3) ? 6 : (NR % 2 == 0 ? NR : 2 * NR);
+  constexpr bool kFixedRing = U % 3 == 0;
+  constexpr int NF = kInPlace ? NR : 2;  // FP32 rows of the first step
+  __shared__ float psa[3][NT];    // psi(t) rows
+  __shared__ float fs[3][9][NT];  // f*(t + 1) rows, as read back from storage
+  __shared__ float psb[3][NT];    // psi(t + 1) rows
+  const int nitems = *nitems_p;
+  const int t = threadIdx.x;
+  const bool stage_a = t >= 1 && t <= NT - 2;
+  const bool stage_b = t >= 2 && t <= NT - 3;
+  // Lanes that store nothing still run the last collision (on clamped ring
+  // columns) so that the row's stores need no branch.
+  const int tf = min(max(t, 1), NT - 2);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
+    const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
+    if (sub < dp->nsub) {
+      F s;
+      s.setup(dp, ti, sub);
+      const int h = s.h;
+      // With constant ring slots the march is instantiated per direction, so
+      // that every ring access is the lane's LDS address plus a constant.  In
+      // march order the row below a row (y - 1) is the previous one when
+      // marching downwards and the next one when marching upwards.
+      auto march = [&](auto upward) {
+      const int below = upward ? 1 : -1;
+      RawCell<S> raw[kInPlace ? 1 : NR];
+      float fa[NF][10], fb[2][10];
+      // Row R (>= -3) of the first step is loaded into slot R mod NR.
+      auto fetch_row = [&](int row, auto slot_c) {
+        constexpr int k = decltype(slot_c)::value;
+        if constexpr (kInPlace)
+          s.fetch(row, fa[k], nullptr);
+        else
+          s.fetch(row, raw[k].v, raw[k].q);
+      };
+      unrolled(std::make_integer_sequence<int, PF>{}, [&](auto k) {
+        fetch_row(-3 + decltype(k)::value,
+                  std::integral_constant<int, (decltype(k)::value + 3 * NR - 3) % NR>{});
+      });
+      // March position j with phase u = j mod U: issue the loads of row
+      // j + 3 + PF (the band's last row again past its end); decode row j + 3
+      // and publish psi(t); collide row j + 2 into the ring; pull f(t + 1) of
+      // row j + 1 and publish psi(t + 1); collide row j and store it.
+      auto pos = [&](auto lead_c, auto u_c, int j) {
+        constexpr bool kLead = decltype(lead_c)::value;  // j < 0: no output row yet
+        constexpr int u = decltype(u_c)::value;
+        constexpr int kd = (u + 3) % NR;  // slot of row j + 3
+        // ring slot of row j + d (j = u mod U)
+        auto ring = [&](int d) { return kFixedRing ? (u + d + 9) % 3 : slot3(j + d); };
+        float(&fa_c)[10] = fa[kInPlace ? kd : (u + 3) & 1];
+        float(&fa_p)[10] = fa[kInPlace ? (u + 2) % NR : (u + 2) & 1];
+        float(&fb_c)[10] = fb[(u + 1) & 1];
+        float(&fb_p)[10] = fb[u & 1];
+        fetch_row(min(j + 3 + PF, h + 2), std::integral_constant<int, (u + 3 + PF) % NR>{});
+        if constexpr (kInPlace)
+          fa_c[9] = density(fa_c);
+        else
+          s.decode(raw[kd], fa_c);
+        psa[ring(3)][t] = psi_of(fa_c[9]);
+        __syncthreads();
+        if ((!kLead || j >= -4) && stage_a) {  // row j + 2
+          float Fx, Fy;
+          ring_force(psa[ring(2 + below)], psa[ring(2)], psa[ring(2 - below)], t, s.G, Fx, Fy);
+          const float rho = fa_p[9];
+          collide(fa_p, rho, Fx, Fy, s.tau, s.omega);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fs[ring(2)][i][t] = s.through_storage(fa_p[i], i, rho);
+        }
+        __syncthreads();
+        if ((!kLead || j >= -2) && stage_b) {
+          // row j + 1: f_i(x) = f*_i(x - e_i), rows below feed e_iy = +1
+          const float(*dn)[NT] = fs[ring(1 + below)];
+          const float(*md)[NT] = fs[ring(1)];
+          const float(*up)[NT] = fs[ring(1 - below)];
+          fb_c[0] = md[0][t];
+          fb_c[1] = md[1][t - 1];
+          fb_c[2] = dn[2][t];
+          fb_c[3] = md[3][t + 1];
+          fb_c[4] = up[4][t];
+          fb_c[5] = dn[5][t - 1];
+          fb_c[6] = dn[6][t + 1];
+          fb_c[7] = up[7][t + 1];
+          fb_c[8] = up[8][t - 1];
+          fb_c[9] = density(fb_c);
+          psb[ring(1)][t] = psi_of(fb_c[9]);
+        }
+        __syncthreads();
+        if constexpr (!kLead) {
+          float Fx, Fy;
+          ring_force(psb[ring(below)], psb[ring(0)], psb[ring(-below)], tf, s.G, Fx, Fy);
+          collide(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
+          s.store(j, fb_p);
+        }
+      };
+      // six lead-in positions, j = -6 .. -1
+      unrolled(std::make_integer_sequence<int, 6>{}, [&](auto k) {
+        constexpr int j = decltype(k)::value - 6;
+        pos(std::true_type{}, std::integral_constant<int, (j % U + U) % U>{}, j);
+      });
+      const auto phases = std::make_integer_sequence<int, U>{};
+      int j0 = 0;
+      for (; j0 + U <= h; j0 += U)
+        unrolled(phases, [&](auto u) { pos(std::false_type{}, u, j0 + decltype(u)::value); });
+      unrolled(std::make_integer_sequence<int, U - 1>{}, [&](auto u) {
+        if (j0 + decltype(u)::value < h) pos(std::false_type{}, u, j0 + decltype(u)::value);
+      });
+      };
+      if constexpr (!kFixedRing)
+        march(s.dir != 0);
+      else if (s.dir)
+        march(std::true_type{});
+      else
+        march(std::false_type{});
+    }
+    __syncthreads();  // the next item reuses the rings
   }
 }
 

@@ -140,10 +140,24 @@ int default_strip_tile(const lbm_params& p) {
 }
 
 int default_tile(const lbm_params& p) {
+  const size_t cells = (size_t)p.nx * (size_t)p.ny;
+  // From a million cells up, two steps per launch wherever that measured
+  // faster: FP32 (256 threads from 4M cells with 8-row bands, else 128 with
+  // 4-row bands) and FP16-shifted (128 threads; 32-, 16- and 4-row bands from
+  // 16M, 4M and 1M cells); FP16 shifted per cell from 16M cells (256
+  // threads, 2 rows in flight, 32-row bands).
+  if (p.storage == LBM_F32 && cells >= (1u << 20)) {
+    const bool big = cells >= (4u << 20);
+    return find_variant(big ? 256 : 128, 1, 1, 0, 2) * kNumRows + row_choice(big ? 8 : 4);
+  }
+  if (p.storage == LBM_F16_SHIFTED && cells >= (1u << 20))
+    return find_variant(128, 1, 1, 0, 2) * kNumRows +
+           row_choice(cells >= (16u << 20) ? 32 : (cells >= (4u << 20) ? 16 : 4));
+  if (p.storage == LBM_F16_CELL && cells >= (16u << 20))
+    return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(32);
   // FP16 storage: paired columns, 4 wavefronts, 2 rows in flight, 4-row
   // bands (2 below a million cells), where the grid allows it.
   if (p.storage != LBM_F32) {
-    const size_t cells = (size_t)p.nx * (size_t)p.ny;
     const int k = find_variant(256, 2, 2, 1) * kNumRows + row_choice(cells >= (1u << 20) ? 4 : 2);
     if (tile_valid(k, p.nx)) return k;
   }

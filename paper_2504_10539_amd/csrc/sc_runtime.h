@@ -37,10 +37,11 @@ inline int tile_width(int k) {
 // Time steps one launch of tile shape k takes.
 inline int tile_steps(int k) { return step_variant(tile_variant(k)).steps; }
 // Index of the step variant with these parameters (-1 if there is none).
-inline int find_variant(int threads, int cells, int prefetch, int paired) {
+inline int find_variant(int threads, int cells, int prefetch, int paired, int steps = 1) {
   for (int v = 0; v < kNumVariants; ++v) {
     const StepVariant& s = step_variant(v);
-    if (s.threads == threads && s.cells == cells && s.prefetch == prefetch && s.paired == paired)
+    if (s.threads == threads && s.cells == cells && s.prefetch == prefetch && s.paired == paired &&
+        s.steps == steps)
       return v;
   }
   return -1;
