@@ -63,7 +63,8 @@ def traffic_from_profiles(lbm, kernel_hash: str, storage: str, n: int, tile: int
         return None
     t = lbm.tiles()[tile]
     code = {"f32": lbm.LBM_F32, "f16_shifted": lbm.LBM_F16_SHIFTED, "f16_cell": lbm.LBM_F16_CELL}[storage]
-    key = (storage, n, kernel_name(lbm, tile, code), t["width"], t["rows"])
+    rows = lbm.tile_layout(n, n, tile, code)[0]  # the band height this grid uses
+    key = (storage, n, kernel_name(lbm, tile, code), t["width"], rows)
     for e in d.get("entries", []):
         if (e.get("storage"), e.get("n"), e.get("kernel"), e.get("width"), e.get("rows")) == key:
             return e.get("bytes_per_launch") if e.get("kernel_hash") == kernel_hash else None
@@ -153,6 +154,7 @@ def run_main(args, torch, lbm, inputs):
             # throughput over the HBM bound of a one-step-per-launch kernel
             "over_one_step_roofline": N * N / (per_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9 / bpu),
             "tile": sim.tile,
+            "band_rows": lbm.tile_layout(N, N, sim.tile, storage)[0],
             "kernel": kernel_name(lbm, sim.tile, storage),
             "metrics": {k: m[k] for k in ("W", "Gmax", "drho", "W_eff", "E_int", "mass", "finite")},
         }
@@ -190,6 +192,7 @@ def run_single_droplet(args, torch, lbm, inputs):
            "step_kernel_ms": ms, "step_kernel_mlups": n * n / (ms * 1e-3) / 1e6,
            "steps_per_launch": lf["steps_per_launch"], "launch_ms": lf["launch_ms"],
            "achieved_gbs": lf["achieved_gbs"], "tile": sim.tile,
+           "band_rows": lbm.tile_layout(n, n, sim.tile, lbm.LBM_F32)[0],
            "kernel": kernel_name(lbm, sim.tile, lbm.LBM_F32),
            "metrics": {k: m[k] for k in ("W", "Gmax", "drho", "W_eff", "E_int", "mass", "finite")}}
     log(f"[single droplet 1024^2] {res['step_kernel_mlups']:.0f} MLUPS per launch, "

@@ -205,12 +205,19 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * need an even nx >= 128 (lbm_set_tile returns LBM_EINVAL otherwise).
  * steps = 2: one launch advances the strip two time steps, the intermediate
  * populations kept on chip (rounded to the storage type as a store would
- * round them); batches and servers use steps = 1 shapes only.  Every shape
- * computes bitwise the same result; only speed differs.  Any output pointer
- * may be NULL; k out of range is LBM_EINVAL. */
+ * round them); batches and servers use steps = 1 shapes only.  rows = 0:
+ * balanced bands, whose height is chosen per grid so that a launch is about
+ * two rounds of the workgroups the device holds at once (lbm_tile_layout
+ * gives it).  Every shape computes bitwise the same result; only speed
+ * differs.  Any output pointer may be NULL; k out of range is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
                              int32_t* prefetch, int32_t* cells, int32_t* paired, int32_t* steps);
+/* Band height (*rows) and number of work items (*items) of tile shape k on a
+ * grid with these parameters.  For a balanced shape the height depends on
+ * the step kernel's occupancy on the current device.  Either output may be
+ * NULL; invalid parameters or k out of range are LBM_EINVAL. */
+lbm_status lbm_tile_layout(const lbm_params* p, int32_t k, int32_t* rows, int32_t* items);
 lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t k);
 int32_t lbm_get_tile(const lbm_ctx* ctx);
 
@@ -218,7 +225,8 @@ int32_t lbm_get_tile(const lbm_ctx* ctx);
  * reading the current buffer and writing the idle one, so the state is not
  * changed), selects the fastest per time step, and records it in the tuning cache
  * (a JSON file named by the SCLBM_TUNE_CACHE environment variable; no file
- * if unset) keyed by device architecture, storage and grid size.
+ * if unset) keyed by device architecture, storage and grid size; entries
+ * written for another tile table are ignored.
  * Synchronises.  *best (may be NULL) receives the chosen shape. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* best);
 

@@ -24,9 +24,13 @@ constexpr int kPairColumns = 124;
 constexpr int kPairMinNx = 128;
 // Band heights a tile shape may use; tile shape k = variant * kNumRows + row
 // index.  The short bands (2, 4 rows) give grids too small to fill the GPU
-// with long bands enough workgroups in flight.
-constexpr int kRowChoices[] = {8, 16, 32, 64, 128, 2, 4};
-constexpr int kNumRows = 7;
+// with long bands enough workgroups in flight.  0 = balanced: the height that
+// makes the grid about two rounds of the workgroups the GPU holds at once
+// (kBalancedRounds), computed per grid, storage and device.
+constexpr int kRowChoices[] = {8, 16, 32, 64, 128, 2, 4, 0};
+constexpr int kNumRows = 8;
+constexpr int kBalancedRounds = 2;
+constexpr int kMaxBalancedRows = 256;
 constexpr int kNumTiles = kNumVariants * kNumRows;
 constexpr int kMinStripWidth = 64;
 constexpr int kMinRows = 2;

@@ -90,8 +90,8 @@ WorkLayout work_layout(int nx, int ny) {
 // Bands alternate their march direction, so the two bands on either side of
 // a band boundary reach the rows they share at the same time (both at the
 // start or both at the end of their march) and read them once from L2.
-void make_items(int nx, int ny, int tile, int inst, std::vector<TileItem>& out) {
-  const int sw = tile_width(tile), rows = tile_rows(tile);
+void make_items(int nx, int ny, int storage, int tile, int inst, std::vector<TileItem>& out) {
+  const int sw = tile_width(tile), rows = band_rows(tile, nx, ny, storage);
   int band = 0;
   for (int y0 = 0; y0 < ny; y0 += rows, ++band)
     for (int x0 = 0; x0 < nx; x0 += sw)
@@ -111,6 +111,29 @@ std::vector<TileItem> xcd_order(const std::vector<TileItem>& items) {
       if (local < chunk && src < std::min(n, (k + 1) * chunk)) out.push_back(items[src]);
     }
   return out;
+}
+
+// Workgroups of a step variant resident on the whole device at once (looked
+// up once per storage type and variant; 4 per CU if the query fails).
+static int resident_blocks(int storage, int variant) {
+  static std::mutex mu;
+  static int known[kNumStorages][kNumVariants] = {};
+  std::lock_guard<std::mutex> lk(mu);
+  int& r = known[storage][variant];
+  if (r == 0) {
+    int per_cu = 0;
+    if (step_occupancy(storage, variant, &per_cu) != hipSuccess || per_cu < 1) per_cu = 4;
+    r = per_cu * device_cu_count();
+  }
+  return r;
+}
+
+int band_rows(int k, int nx, int ny, int storage) {
+  const int r = tile_rows(k);
+  if (r > 0) return r;
+  const int strips = (nx + tile_width(k) - 1) / tile_width(k);
+  const int bands = std::max(1, kBalancedRounds * resident_blocks(storage, tile_variant(k)) / strips);
+  return std::min(std::max((ny + bands - 1) / bands, kMinRows), kMaxBalancedRows);
 }
 
 int row_choice(int rows) {
@@ -143,18 +166,19 @@ int default_tile(const lbm_params& p) {
   const size_t cells = (size_t)p.nx * (size_t)p.ny;
   // From a million cells up, two steps per launch wherever that measured
   // faster: FP32 (256 threads from 4M cells with 8-row bands, else 128 with
-  // 4-row bands) and FP16-shifted (128 threads; 32-, 16- and 4-row bands from
-  // 16M, 4M and 1M cells); FP16 shifted per cell from 16M cells (256
-  // threads, 2 rows in flight, 32-row bands).
+  // 4-row bands); FP16-shifted (from 16M cells 256 threads, 2 rows in
+  // flight, balanced bands; else 128 threads, 16-row bands from 4M cells,
+  // 4-row from 1M); FP16 shifted per cell from 16M cells (as FP16-shifted).
   if (p.storage == LBM_F32 && cells >= (1u << 20)) {
     const bool big = cells >= (4u << 20);
     return find_variant(big ? 256 : 128, 1, 1, 0, 2) * kNumRows + row_choice(big ? 8 : 4);
   }
+  if (p.storage == LBM_F16_SHIFTED && cells >= (16u << 20))
+    return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
   if (p.storage == LBM_F16_SHIFTED && cells >= (1u << 20))
-    return find_variant(128, 1, 1, 0, 2) * kNumRows +
-           row_choice(cells >= (16u << 20) ? 32 : (cells >= (4u << 20) ? 16 : 4));
+    return find_variant(128, 1, 1, 0, 2) * kNumRows + row_choice(cells >= (4u << 20) ? 16 : 4);
   if (p.storage == LBM_F16_CELL && cells >= (16u << 20))
-    return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(32);
+    return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
   // FP16 storage: paired columns, 4 wavefronts, 2 rows in flight, 4-row
   // bands (2 below a million cells), where the grid allows it.
   if (p.storage != LBM_F32) {
@@ -202,9 +226,11 @@ static int size_bucket(int n) {
   return b;
 }
 
+// Each entry also records the size of the tile table it indexes, so entries
+// written by a build with other tile shapes are ignored.
 struct TuneEntry {
   std::string arch;
-  int storage, bx, by, tile;
+  int tiles, storage, bx, by, tile;
   double ms;
 };
 
@@ -216,10 +242,10 @@ static std::vector<TuneEntry> read_tune_cache(const char* path) {
     char arch[64] = {0};
     TuneEntry e{};
     if (sscanf(line.c_str(),
-               "{\"arch\": \"%63[^\"]\", \"storage\": %d, \"bx\": %d, \"by\": %d, \"tile\": %d, "
-               "\"ms\": %lf}",
-               arch, &e.storage, &e.bx, &e.by, &e.tile, &e.ms) == 6 &&
-        e.tile >= 0 && e.tile < kNumTiles) {
+               "{\"arch\": \"%63[^\"]\", \"tiles\": %d, \"storage\": %d, \"bx\": %d, \"by\": %d, "
+               "\"tile\": %d, \"ms\": %lf}",
+               arch, &e.tiles, &e.storage, &e.bx, &e.by, &e.tile, &e.ms) == 7 &&
+        e.tiles == kNumTiles && e.tile >= 0 && e.tile < kNumTiles) {
       e.arch = arch;
       v.push_back(e);
     }
@@ -249,16 +275,16 @@ void record_tuned_tile(const lbm_params& p, const std::string& arch, int tile, d
                                   e.by == by;
                          }),
           v.end());
-  v.push_back({arch, p.storage, bx, by, tile, ms});
+  v.push_back({arch, kNumTiles, p.storage, bx, by, tile, ms});
   const std::string tmp = std::string(path) + ".tmp";
   {
     std::ofstream out(tmp, std::ios::trunc);
     for (const TuneEntry& e : v) {
       char buf[256];
       snprintf(buf, sizeof buf,
-               "{\"arch\": \"%s\", \"storage\": %d, \"bx\": %d, \"by\": %d, \"tile\": %d, "
-               "\"ms\": %.6f}\n",
-               e.arch.c_str(), e.storage, e.bx, e.by, e.tile, e.ms);
+               "{\"arch\": \"%s\", \"tiles\": %d, \"storage\": %d, \"bx\": %d, \"by\": %d, "
+               "\"tile\": %d, \"ms\": %.6f}\n",
+               e.arch.c_str(), e.tiles, e.storage, e.bx, e.by, e.tile, e.ms);
       out << buf;
     }
   }
@@ -289,7 +315,7 @@ InstDesc lbm_ctx::host_desc() const {
 
 lbm_status lbm_ctx::upload_tile(int k) {
   std::vector<TileItem> items;
-  make_items(p.nx, p.ny, k, 0, items);
+  make_items(p.nx, p.ny, p.storage, k, 0, items);
   items = xcd_order(items);
   if ((int)items.size() > lay.max_items) return fail(LBM_EINVAL, "tile table overflow");
   const int n = (int)items.size();
@@ -345,7 +371,7 @@ lbm_status lbm_ctx::series_tiles() {
   if (series_nitems > 0) return LBM_OK;
   const int k = find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + 0;
   std::vector<TileItem> items;
-  make_items(p.nx, p.ny, k, 0, items);
+  make_items(p.nx, p.ny, p.storage, k, 0, items);
   items = xcd_order(items);
   if ((int)items.size() > lay.series_items) return fail(LBM_EINVAL, "series tile table overflow");
   const int ni = (int)items.size();
@@ -520,7 +546,7 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
       const int s = c->p.storage;
       if (grid[s] == 0) return fail(LBM_EINVAL, "batch has no kernel for this storage type");
       std::vector<TileItem> items;
-      make_items(c->p.nx, c->p.ny, member_tile(c, variant[s], tile_override, row_override), i,
+      make_items(c->p.nx, c->p.ny, s, member_tile(c, variant[s], tile_override, row_override), i,
                  items);
       if (count[s] + (int)items.size() > cap_items[s])
         return fail(LBM_ENOMEM, "batch tile table full");
@@ -612,7 +638,7 @@ int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int ti
   for (lbm_ctx* c : m) {
     if (c->p.storage != storage) continue;
     const int k = member_tile(c, variant, tile_override);  // as make_items tiles it
-    const int sw = tile_width(k), rows = tile_rows(k);
+    const int sw = tile_width(k), rows = band_rows(k, c->p.nx, c->p.ny, storage);
     n += ((c->p.nx + sw - 1) / sw) * ((c->p.ny + rows - 1) / rows);
   }
   return n;
@@ -886,6 +912,17 @@ lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* 
   if (cells) *cells = v.cells;
   if (paired) *paired = v.paired;
   if (steps) *steps = v.steps;
+  return LBM_OK;
+}
+
+lbm_status lbm_tile_layout(const lbm_params* p, int32_t k, int32_t* rows, int32_t* items) {
+  const lbm_status v = validate_params(p);
+  if (v != LBM_OK) return v;
+  if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+  const int r = band_rows(k, p->nx, p->ny, p->storage);
+  const int w = tile_width(k);
+  if (rows) *rows = r;
+  if (items) *items = ((p->nx + w - 1) / w) * ((p->ny + r - 1) / r);
   return LBM_OK;
 }
 

@@ -28,7 +28,7 @@ size_t align_up(size_t v, size_t a);
 
 // Tile shape k -> (variant, rows).
 inline int tile_variant(int k) { return k / kNumRows; }
-inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }
+inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }  // 0: balanced
 inline int tile_width(int k) {
   const StepVariant& v = step_variant(tile_variant(k));
   if (v.steps == 2) return v.threads - kFusedHalo;
@@ -54,8 +54,11 @@ inline bool tile_valid(int k, int nx) {
 // Whether a batch can use tile shape k (batches take one step per launch).
 inline bool tile_batchable(int k, int nx) { return tile_valid(k, nx) && tile_steps(k) == 1; }
 
+// Band height tile shape k uses on an nx x ny grid of this storage type
+// (balanced shapes: from the step kernel's occupancy on the current device).
+int band_rows(int k, int nx, int ny, int storage);
 // Work items of one grid for tile shape k, appended for simulation `inst`.
-void make_items(int nx, int ny, int tile, int inst, std::vector<TileItem>& out);
+void make_items(int nx, int ny, int storage, int tile, int inst, std::vector<TileItem>& out);
 // Reorders items so that the workgroups a hardware XCD receives (workgroup
 // ids congruent mod 8) cover a contiguous run of the original order.
 std::vector<TileItem> xcd_order(const std::vector<TileItem>& items);

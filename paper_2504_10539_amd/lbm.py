@@ -119,6 +119,7 @@ _PROTOS = {
     "lbm_tile_count": (_i32, []),
     "lbm_tile_describe": (_i32, [_i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32),
                                  _P(_i32), _P(_i32)]),
+    "lbm_tile_layout": (_i32, [_P(lbm_params), _i32, _P(_i32), _P(_i32)]),
     "lbm_set_tile": (_i32, [_vp, _i32]),
     "lbm_get_tile": (_i32, [_vp]),
     "lbm_autotune": (_i32, [_vp, _i32, _P(_i32)]),
@@ -246,6 +247,15 @@ def tiles() -> list[dict]:
                     "prefetch": p.value, "cells": c.value, "paired": pa.value,
                     "steps": st.value})
     return out
+
+
+def tile_layout(nx: int, ny: int, k: int, storage: int = LBM_F32) -> tuple[int, int]:
+    """(band height, work items) of tile shape k on an nx x ny grid."""
+    p = make_params(nx, ny, -5.0, 1.0, storage, 1.0 if storage == LBM_F16_SHIFTED else 0.0)
+    rows, items = _i32(), _i32()
+    _check(LIB.lbm_tile_layout(ctypes.byref(p), int(k), ctypes.byref(rows), ctypes.byref(items)),
+           "lbm_tile_layout")
+    return rows.value, items.value
 
 
 class Simulation:

@@ -104,7 +104,7 @@ def test_buffer_sizes_and_validation(lbm):
 def test_tile_table(lbm):
     tiles = lbm.tiles()
     assert len(tiles) == lbm.LIB.lbm_tile_count()
-    assert all(t["width"] >= 64 and t["rows"] >= 2 for t in tiles)
+    assert all(t["width"] >= 64 and (t["rows"] >= 2 or t["rows"] == 0) for t in tiles)
     assert len({(t["width"], t["rows"], t["threads"], t["prefetch"]) for t in tiles}) == len(tiles)
     w = ctypes.c_int32()
     assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None, None,
@@ -118,3 +118,24 @@ def test_tile_table(lbm):
         else:
             assert t["width"] == t["threads"] * t["cells"]
     assert any(t["steps"] == 2 for t in tiles)
+
+
+def test_tile_layout(lbm):
+    """Band height and item count a shape uses on a grid; balanced shapes pick
+    a height in [2, 256] (from the device's occupancy; without a device from a
+    fallback of 4 workgroups per CU)."""
+    tiles = lbm.tiles()
+    for t in tiles:
+        rows, items = lbm.tile_layout(300, 77, t["id"])
+        if t["rows"]:
+            assert rows == t["rows"]
+        else:
+            assert 2 <= rows <= 256
+        assert items == -(-300 // t["width"]) * -(-77 // rows)
+    bal = next(t for t in tiles if t["rows"] == 0 and t["steps"] == 2 and t["threads"] == 256)
+    rows, items = lbm.tile_layout(4096, 4096, bal["id"], lbm.LBM_F16_SHIFTED)
+    assert 2 <= rows <= 256 and items == 17 * -(-4096 // rows)
+    r = ctypes.c_int32()
+    assert lbm.LIB.lbm_tile_layout(None, 0, ctypes.byref(r), None) == lbm.LBM_EINVAL
+    p = lbm.make_params(64, 64, -5.0, 1.0)
+    assert lbm.LIB.lbm_tile_layout(ctypes.byref(p), len(tiles), None, None) == lbm.LBM_EINVAL
