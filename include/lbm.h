@@ -205,11 +205,11 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * need an even nx >= 128 (lbm_set_tile returns LBM_EINVAL otherwise).
  * steps = 2: one launch advances the strip two time steps, the intermediate
  * populations kept on chip (rounded to the storage type as a store would
- * round them); batches and servers use steps = 1 shapes only.  rows = 0:
- * balanced bands, whose height is chosen per grid so that a launch is about
- * two rounds of the workgroups the device holds at once (lbm_tile_layout
- * gives it).  Every shape computes bitwise the same result; only speed
- * differs.  Any output pointer may be NULL; k out of range is LBM_EINVAL. */
+ * round them).  rows = 0: balanced bands, whose height is chosen per grid so
+ * that a launch is about two rounds of the workgroups the device holds at
+ * once (lbm_tile_layout gives it).  Every shape computes bitwise the same
+ * result; only speed differs.  Any output pointer may be NULL; k out of range
+ * is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
                              int32_t* prefetch, int32_t* cells, int32_t* paired, int32_t* steps);
@@ -237,8 +237,10 @@ lbm_status lbm_batch_work_bytes(lbm_ctx* const* ctxs, int32_t n, size_t* bytes);
 
 /* Groups n >= 1 contexts created on the same stream into one batch that
  * advances all of them with one persistent multi-instance kernel launch per
- * time step (one per storage type present), `steps_per_graph` launches
- * captured in a HIP graph and replayed.  The per-cell arithmetic is the same
+ * time step (one per storage type present), `steps_per_graph` steps captured
+ * in a HIP graph and replayed.  Each storage type uses the step shape of its
+ * widest member's tile: with a two-step shape, one launch per two steps and a
+ * single-step launch for a member's odd last step of a replay.  The per-cell arithmetic is the same
  * code as lbm_step_n, so every member's result is bitwise the one it would
  * have alone.  The contexts are borrowed and must not be stepped on their own
  * (LBM_EBUSY) until lbm_batch_destroy; metrics, moments and state copies on a

@@ -20,7 +20,10 @@ constexpr float kW2 = 1.0f / 36.0f;
 
 // Per-simulation record read by the step kernels.  pop[0]/pop[1] are the two
 // population buffers; the state before launch `sub` of a sequence sits in
-// pop[(parity + sub) & 1] and launch `sub` runs only while sub < nsub.
+// pop[(parity + sub) & 1].  nsub is the number of time steps of the sequence
+// (the steps of one batched tick): single-step launches run while sub <
+// nsub; two-step launches while sub < nsub / 2; with two-step launches an odd
+// nsub ends with one single-step tail launch (sub = kTailSub).
 struct InstDesc {
   uint64_t pop[2];
   int32_t nx, ny;
@@ -30,9 +33,29 @@ struct InstDesc {
   int64_t remaining;  // batched runs: steps still to take
   int64_t steps;      // batched runs: steps taken
   int32_t storage;
-  int32_t pad[3];
+  int32_t two_step;   // batched runs: advanced by two-step launches (and a tail)
+  int32_t pad[2];
 };
 static_assert(sizeof(InstDesc) == 80, "InstDesc layout");
+
+constexpr int kTailSub = -1;
+
+// Whether single-step launch `sub` runs for this simulation, and the buffer
+// it reads (the tail launch follows the nsub / 2 two-step launches).
+__host__ __device__ __forceinline__ bool step_runs(const InstDesc* d, int sub) {
+  return sub >= 0 ? sub < d->nsub : (d->nsub & 1) != 0;
+}
+__host__ __device__ __forceinline__ int step_parity(const InstDesc* d, int sub) {
+  return (d->parity + (sub >= 0 ? sub : d->nsub >> 1)) & 1;
+}
+// Whether two-step launch `sub` runs (it reads pop[(parity + sub) & 1]).
+__host__ __device__ __forceinline__ bool pair_runs(const InstDesc* d, int sub) {
+  return sub < (d->nsub >> 1);
+}
+// Buffer swaps of a tick of n steps: one per launch.
+__host__ __device__ __forceinline__ int64_t tick_flips(int64_t n, bool two_step) {
+  return two_step ? (n >> 1) + (n & 1) : n;
+}
 
 // One unit of step-kernel work: rows [y0, y0 + h) of the strip of columns
 // starting at x0 of simulation `inst`, marched downwards (dir = 0, from y0)

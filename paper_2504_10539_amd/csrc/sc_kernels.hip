@@ -88,7 +88,7 @@ struct Strip {
     tau = dp->tau;
     omega = dp->omega;
     const float rho0 = dp->rho0;
-    const int par = (dp->parity + sub) & 1;
+    const int par = step_parity(dp, sub);
     const uint64_t a = dp->pop[0], b = dp->pop[1];
     src = par ? b : a;
     dst = par ? a : b;
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
-    if (sub < dp->nsub) {
+    if (step_runs(dp, sub)) {
       St s;
       s.setup(dp, ti, sub);
       march<St, PF>(s, ring);
@@ -579,7 +579,7 @@ struct PairStrip {
     tau = dp->tau;
     omega = dp->omega;
     const float rho0 = dp->rho0;
-    const int par = (dp->parity + sub) & 1;
+    const int par = step_parity(dp, sub);
     const uint64_t a = dp->pop[0], b = dp->pop[1];
     src = par ? b : a;
     dst = par ? a : b;
@@ -723,7 +723,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
-    if (sub < dp->nsub && ti.x0 + wave * kPairOut < dp->nx) {
+    if (step_runs(dp, sub) && ti.x0 + wave * kPairOut < dp->nx) {
       St s;
       s.setup(dp, ti, sub, wave, lane);
       const int h = s.h;
@@ -839,7 +839,7 @@ struct Fused2 {
     tau = dp->tau;
     omega = dp->omega;
     const float rho0 = dp->rho0;
-    const int par = (dp->parity + sub) & 1;
+    const int par = (dp->parity + sub) & 1;  // sub >= 0
     const uint64_t a = dp->pop[0], b = dp->pop[1];
     src = par ? b : a;
     dst = par ? a : b;
@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
-    if (sub < dp->nsub) {
+    if (pair_runs(dp, sub)) {
       F s;
       s.setup(dp, ti, sub);
       const int h = s.h;
@@ -1132,12 +1132,13 @@ __global__ void k_batch_arm(InstDesc* descs, int n, int64_t steps) {
   }
 }
 
-// End of a graph replay: account for the steps taken.
+// End of a graph replay: account for the steps taken (one buffer swap per
+// launch that ran).
 __global__ void k_tick_end(InstDesc* descs, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const int32_t s = descs[i].nsub;
-    descs[i].parity = (descs[i].parity + s) & 1;
+    descs[i].parity = (int32_t)((descs[i].parity + tick_flips(s, descs[i].two_step != 0)) & 1);
     descs[i].remaining -= s;
     descs[i].steps += s;
     descs[i].nsub = 0;

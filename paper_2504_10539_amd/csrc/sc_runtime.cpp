@@ -458,25 +458,45 @@ hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
                           size_t nd, bool begin, InstDesc* descs, int n, int K);
 hipError_t launch_batch_arm(InstDesc* descs, int n, int64_t steps, hipStream_t st);
 
-size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[kNumStorages], int K) {
+size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[kNumStorages],
+                               const int cap_titems[kNumStorages], int K) {
+  (void)K;
   size_t o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
-  for (int s = 0; s < kNumStorages; ++s)
+  for (int s = 0; s < kNumStorages; ++s) {
     o += 256 + align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
+    if (cap_titems[s] > 0) o += 256 + align_up((size_t)cap_titems[s] * sizeof(TileItem), 256);
+  }
   return o;
+}
+
+int tail_variant_for(int variant) {
+  return step_variant(variant).steps == 2 ? find_variant(kSeriesThreads, 1, 2, 0) : -1;
 }
 
 lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
                              const int cap_items_[kNumStorages],
+                             const int cap_titems_[kNumStorages],
                              const int variants[kNumStorages], void* work, size_t wbytes) {
   stream = st;
   K = steps_per_tick;
   cap_inst = cap_inst_;
-  if (wbytes < work_bytes(cap_inst, cap_items_, K)) return fail(LBM_ENOMEM, "batch workspace too small");
+  if (wbytes < work_bytes(cap_inst, cap_items_, cap_titems_, K))
+    return fail(LBM_ENOMEM, "batch workspace too small");
   char* w = reinterpret_cast<char*>(work);
   size_t o = 0;
   d_desc = reinterpret_cast<InstDesc*>(w);
   o = align_up((size_t)cap_inst * sizeof(InstDesc), 256);
   const int cus = device_cu_count();
+  // Persistent engines (item counts change between replays) run a grid sized
+  // to the resident capacity; fixed ones launch one workgroup per item, so
+  // the hardware overlaps one item's tail with the next item's loads.
+  auto grid_for = [&](int s, int v, int cap, int* g) -> lbm_status {
+    int occ = 0;
+    SCLBM_HIP(step_occupancy(s, v, &occ));
+    const int res = std::max(8, std::max(occ, 1) * cus / 8 * 8);
+    *g = persistent ? std::min(cap, res) : cap;
+    return LBM_OK;
+  };
   for (int s = 0; s < kNumStorages; ++s) {
     cap_items[s] = cap_items_[s];
     variant[s] = variants[s];
@@ -484,39 +504,66 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
     o += 256;
     d_items[s] = reinterpret_cast<TileItem*>(w + o);
     o += align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
-    grid[s] = 0;
+    grid[s] = tgrid[s] = 0;
+    cap_titems[s] = cap_titems_[s];
+    tail_variant[s] = -1;
+    if (cap_titems[s] > 0) {
+      d_tnitems[s] = reinterpret_cast<int*>(w + o);
+      o += 256;
+      d_titems[s] = reinterpret_cast<TileItem*>(w + o);
+      o += align_up((size_t)cap_titems[s] * sizeof(TileItem), 256);
+    }
     if (variant[s] < 0 || cap_items[s] == 0) continue;
-    int occ = 0;
-    SCLBM_HIP(step_occupancy(s, variant[s], &occ));
-    // Persistent engines (item counts change between replays) run a grid
-    // sized to the resident capacity; fixed ones launch one workgroup per
-    // item, so the hardware overlaps one item's tail with the next item's loads.
-    const int cap = std::max(8, std::max(occ, 1) * cus / 8 * 8);
-    grid[s] = persistent ? std::min(cap_items[s], cap) : cap_items[s];
+    lbm_status r = grid_for(s, variant[s], cap_items[s], &grid[s]);
+    if (r != LBM_OK) return r;
+    if (two_step(s)) {
+      if (cap_titems[s] == 0) return fail(LBM_EINVAL, "two-step batch without a tail table");
+      tail_variant[s] = tail_variant_for(variant[s]);
+      r = grid_for(s, tail_variant[s], cap_titems[s], &tgrid[s]);
+      if (r != LBM_OK) return r;
+    }
   }
   for (int b = 0; b < 2; ++b)
     SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_desc[b]),
                             (size_t)cap_inst * sizeof(InstDesc), hipHostMallocDefault));
   for (int s = 0; s < kNumStorages; ++s)
-    if (cap_items[s] > 0)
-      for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
+      if (cap_items[s] > 0)
         SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_items[s][b]),
                                 (size_t)cap_items[s] * sizeof(TileItem) + 64,
                                 hipHostMallocDefault));
+      if (cap_titems[s] > 0)
+        SCLBM_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_titems[s][b]),
+                                (size_t)cap_titems[s] * sizeof(TileItem) + 64,
+                                hipHostMallocDefault));
+    }
   for (int b = 0; b < 2; ++b)
     SCLBM_HIP(hipEventCreateWithFlags(&staged[b], hipEventDisableTiming));
-  // Graph: tick_begin -> K x (one persistent step launch per storage type) -> tick_end.
+  // Graph: tick_begin -> the step launches of every storage type (K single
+  // steps, or ceil(K / 2) two-step launches and a tail) -> tick_end.
   SCLBM_HIP(hipGraphCreate(&graph, 0));
   hipGraphNode_t prev;
   SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K));
-  for (int j = 0; j < K; ++j)
+  int launches[kNumStorages], most = 0;
+  for (int s = 0; s < kNumStorages; ++s) {
+    launches[s] = grid[s] == 0 ? 0 : (two_step(s) ? (K + 1) / 2 : K);
+    most = std::max(most, launches[s]);
+  }
+  for (int j = 0; j < most; ++j)
     for (int s = 0; s < kNumStorages; ++s) {
-      if (grid[s] == 0) continue;
+      if (j >= launches[s]) continue;
       hipGraphNode_t node;
       SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, variant[s], d_desc, d_items[s],
                                d_nitems[s], grid[s], j));
       prev = node;
     }
+  for (int s = 0; s < kNumStorages; ++s) {
+    if (grid[s] == 0 || !two_step(s)) continue;
+    hipGraphNode_t node;
+    SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, tail_variant[s], d_desc, d_titems[s],
+                             d_tnitems[s], tgrid[s], kTailSub));
+    prev = node;
+  }
   hipGraphNode_t last;
   SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K));
   SCLBM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
@@ -532,7 +579,7 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
   stage ^= 1;
   if (staged_pending[sb]) SCLBM_HIP(hipEventSynchronize(staged[sb]));
   InstDesc* hd = h_desc[sb];
-  int count[kNumStorages] = {};
+  int count[kNumStorages] = {}, tcount[kNumStorages] = {};
   for (int i = 0; i < cap_inst; ++i) {
     InstDesc d{};
     d.nsub = 0;
@@ -545,31 +592,46 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
       d.steps = c->steps;
       const int s = c->p.storage;
       if (grid[s] == 0) return fail(LBM_EINVAL, "batch has no kernel for this storage type");
+      d.two_step = two_step(s) ? 1 : 0;
+      const int k = member_tile(c, variant[s], tile_override, row_override);
       std::vector<TileItem> items;
-      make_items(c->p.nx, c->p.ny, s, member_tile(c, variant[s], tile_override, row_override), i,
-                 items);
+      make_items(c->p.nx, c->p.ny, s, k, i, items);
       if (count[s] + (int)items.size() > cap_items[s])
         return fail(LBM_ENOMEM, "batch tile table full");
       std::copy(items.begin(), items.end(), h_items[s][sb] + count[s]);
       count[s] += (int)items.size();
+      if (d.two_step) {  // the tail launch's items: same band height
+        items.clear();
+        make_items(c->p.nx, c->p.ny, s, tail_variant[s] * kNumRows + k % kNumRows, i, items);
+        if (tcount[s] + (int)items.size() > cap_titems[s])
+          return fail(LBM_ENOMEM, "batch tile table full");
+        std::copy(items.begin(), items.end(), h_titems[s][sb] + tcount[s]);
+        tcount[s] += (int)items.size();
+      }
     }
     hd[i] = d;
   }
   SCLBM_HIP(hipMemcpyAsync(d_desc, hd, (size_t)cap_inst * sizeof(InstDesc),
                            hipMemcpyHostToDevice, stream));
-  for (int s = 0; s < kNumStorages; ++s) {
-    if (cap_items[s] == 0) continue;
-    TileItem* hi = h_items[s][sb];
-    std::vector<TileItem> v(hi, hi + count[s]);
+  auto upload = [&](TileItem* hi, int cap, int n, TileItem* d_it, int* d_n) -> lbm_status {
+    std::vector<TileItem> v(hi, hi + n);
     v = xcd_order(v);
     std::copy(v.begin(), v.end(), hi);
-    int* hn = reinterpret_cast<int*>(hi + cap_items[s]);
-    *hn = count[s];
+    int* hn = reinterpret_cast<int*>(hi + cap);
+    *hn = n;
+    if (n > 0)
+      SCLBM_HIP(hipMemcpyAsync(d_it, hi, (size_t)n * sizeof(TileItem), hipMemcpyHostToDevice,
+                               stream));
+    SCLBM_HIP(hipMemcpyAsync(d_n, hn, sizeof(int), hipMemcpyHostToDevice, stream));
+    return LBM_OK;
+  };
+  for (int s = 0; s < kNumStorages; ++s) {
+    if (cap_items[s] == 0) continue;
     nitems[s] = count[s];
-    if (count[s] > 0)
-      SCLBM_HIP(hipMemcpyAsync(d_items[s], hi, (size_t)count[s] * sizeof(TileItem),
-                               hipMemcpyHostToDevice, stream));
-    SCLBM_HIP(hipMemcpyAsync(d_nitems[s], hn, sizeof(int), hipMemcpyHostToDevice, stream));
+    lbm_status r = upload(h_items[s][sb], cap_items[s], count[s], d_items[s], d_nitems[s]);
+    if (r == LBM_OK && cap_titems[s] > 0)
+      r = upload(h_titems[s][sb], cap_titems[s], tcount[s], d_titems[s], d_tnitems[s]);
+    if (r != LBM_OK) return r;
   }
   SCLBM_HIP(hipEventRecord(staged[sb], stream));
   staged_pending[sb] = true;
@@ -598,11 +660,13 @@ void BatchEngine::destroy() {
     staged_pending[b] = false;
   }
   for (int s = 0; s < kNumStorages; ++s)
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 2; ++b) {
       if (h_items[s][b]) (void)hipHostFree(h_items[s][b]);
+      if (h_titems[s][b]) (void)hipHostFree(h_titems[s][b]);
+      h_items[s][b] = h_titems[s][b] = nullptr;
+    }
   exec = nullptr;
   graph = nullptr;
-  for (int s = 0; s < kNumStorages; ++s) h_items[s][0] = h_items[s][1] = nullptr;
 }
 
 // Tile a member uses inside a batch: the batch's override if set, else the
@@ -613,10 +677,9 @@ int member_tile(const lbm_ctx* c, int variant, int tile_override, int row_overri
   return variant * kNumRows + (row_override >= 0 ? row_override : c->tile % kNumRows);
 }
 
-// Strip variant used for one storage type: that of the widest member's tile.
+// Step variant used for one storage type: that of the widest member's tile.
 // A paired-column variant is kept only if every member of that storage type
-// can run it, and a two-step variant never; otherwise the widest member's
-// default strip variant is used.
+// can run it; otherwise the widest member's default strip variant is used.
 int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   int best = -1, bestn = -1;
   const lbm_ctx* widest = nullptr;
@@ -633,11 +696,13 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
   return best;
 }
 
-int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override) {
+int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override,
+                bool tail) {
   int n = 0;
   for (lbm_ctx* c : m) {
     if (c->p.storage != storage) continue;
-    const int k = member_tile(c, variant, tile_override);  // as make_items tiles it
+    int k = member_tile(c, variant, tile_override);  // as make_items tiles it
+    if (tail) k = tail_variant_for(variant) * kNumRows + k % kNumRows;
     const int sw = tile_width(k), rows = band_rows(k, c->p.nx, c->p.ny, storage);
     n += ((c->p.nx + sw - 1) / sw) * ((c->p.ny + rows - 1) / rows);
   }
@@ -659,6 +724,7 @@ namespace {
 struct BatchShape {
   int variants[kNumStorages];
   int items[kNumStorages];
+  int titems[kNumStorages];  // tail items of two-step variants
 };
 
 BatchShape batch_shape(const std::vector<lbm_ctx*>& m, int tile_override = -1) {
@@ -666,7 +732,11 @@ BatchShape batch_shape(const std::vector<lbm_ctx*>& m, int tile_override = -1) {
   for (int s = 0; s < kNumStorages; ++s) {
     b.variants[s] = pick_variant(m, s);
     if (b.variants[s] >= 0 && tile_override >= 0) b.variants[s] = tile_variant(tile_override);
-    b.items[s] = b.variants[s] < 0 ? 0 : count_items(m, s, b.variants[s], tile_override);
+    const bool used = b.variants[s] >= 0;
+    b.items[s] = used ? count_items(m, s, b.variants[s], tile_override) : 0;
+    b.titems[s] = used && step_variant(b.variants[s]).steps == 2
+                      ? count_items(m, s, b.variants[s], tile_override, true)
+                      : 0;
   }
   return b;
 }
@@ -679,8 +749,8 @@ lbm_status batch_rebuild(lbm_batch* b, int tile_override, int nsub_init) {
   b->eng = BatchEngine();
   b->eng.tile_override = tile_override;
   const BatchShape shape = batch_shape(b->members, tile_override);
-  lbm_status r = b->eng.init(st, b->K, (int)b->members.size(), shape.items, shape.variants,
-                             b->work, b->work_bytes);
+  lbm_status r = b->eng.init(st, b->K, (int)b->members.size(), shape.items, shape.titems,
+                             shape.variants, b->work, b->work_bytes);
   if (r == LBM_OK) r = b->eng.load(b->members, std::vector<int64_t>(b->members.size(), 0), nsub_init);
   return r;
 }
@@ -693,7 +763,10 @@ BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) {
     for (lbm_ctx* c : m) valid = valid && tile_batchable(k, c->p.nx);
     if (!valid) continue;
     const BatchShape t = batch_shape(m, k);
-    for (int s = 0; s < kNumStorages; ++s) b.items[s] = std::max(b.items[s], t.items[s]);
+    for (int s = 0; s < kNumStorages; ++s) {
+      b.items[s] = std::max(b.items[s], t.items[s]);
+      b.titems[s] = std::max(b.titems[s], t.titems[s]);
+    }
   }
   return b;
 }
@@ -991,7 +1064,7 @@ lbm_status lbm_batch_work_bytes(lbm_ctx* const* ctxs, int32_t n, size_t* bytes) 
   for (lbm_ctx* c : m)
     if (!c) return fail(LBM_EINVAL, "NULL context in batch");
   const BatchShape b = batch_shape_max(m);
-  *bytes = BatchEngine::work_bytes(n, b.items, kMaxGraphSteps);
+  *bytes = BatchEngine::work_bytes(n, b.items, b.titems, kMaxGraphSteps);
   return LBM_OK;
 }
 
@@ -1018,8 +1091,8 @@ lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* work, size_t 
   b->work = work;
   b->work_bytes = work_bytes;
   b->K = steps_per_graph;
-  lbm_status st = b->eng.init(m[0]->stream, steps_per_graph, n, shape.items, shape.variants, work,
-                              work_bytes);
+  lbm_status st = b->eng.init(m[0]->stream, steps_per_graph, n, shape.items, shape.titems,
+                              shape.variants, work, work_bytes);
   if (st == LBM_OK) st = b->eng.load(m, std::vector<int64_t>(m.size(), 0));
   if (st != LBM_OK) {
     b->eng.destroy();
@@ -1039,9 +1112,12 @@ lbm_status lbm_batch_step_n(lbm_batch* b, int64_t n) {
   const int64_t replays = (n + b->eng.K - 1) / b->eng.K;
   for (int64_t r = 0; r < replays && st == LBM_OK; ++r) st = b->eng.replay();
   if (st != LBM_OK) return st;
+  const int64_t K = b->eng.K;
   for (lbm_ctx* c : b->members) {
+    const bool two = b->eng.two_step(c->p.storage);
+    const int64_t flips = (n / K) * tick_flips(K, two) + tick_flips(n % K, two);
     c->steps += n;
-    c->parity = (int)((c->parity + n) & 1);
+    c->parity = (int)((c->parity + flips) & 1);
   }
   return LBM_OK;
 }
@@ -1059,9 +1135,11 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
     bool valid = true;
     for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx);
     if (!valid) continue;
-    // Every member takes one step per launch from its current buffer into its
-    // idle one and the descriptors are not advanced: the state is unchanged.
-    st = batch_rebuild(b, k, 1);
+    // Every member takes one step (two with a two-step shape) per launch from
+    // its current buffer into its idle one, and the descriptors are not
+    // advanced: the state is unchanged.  Compared per time step.
+    const int per = tile_steps(k);
+    st = batch_rebuild(b, k, per);
     if (st == LBM_ENOMEM) {  // this shape's tables do not fit the workspace
       st = LBM_OK;
       continue;
@@ -1087,8 +1165,8 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
       st = hip_fail(e, "batch autotune launch");
       break;
     }
-    if (ms / reps < best_ms) {
-      best_ms = ms / reps;
+    if (ms / reps / per < best_ms) {
+      best_ms = ms / reps / per;
       best = k;
     }
   }

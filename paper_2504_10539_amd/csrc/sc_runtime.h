@@ -51,8 +51,8 @@ inline bool tile_valid(int k, int nx) {
   const StepVariant& v = step_variant(tile_variant(k));
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
-// Whether a batch can use tile shape k (batches take one step per launch).
-inline bool tile_batchable(int k, int nx) { return tile_valid(k, nx) && tile_steps(k) == 1; }
+// Whether a batch can use tile shape k.
+inline bool tile_batchable(int k, int nx) { return tile_valid(k, nx); }
 
 // Band height tile shape k uses on an nx x ny grid of this storage type
 // (balanced shapes: from the step kernel's occupancy on the current device).
@@ -85,23 +85,33 @@ std::string device_arch();
 int device_cu_count();
 
 // Multi-simulation stepping: a device descriptor table and one tile table per
-// storage type, advanced by a HIP graph of K persistent step launches between
-// a tick-begin and a tick-end kernel.  The graph reads the tables from device
-// memory, so members can change between replays without rebuilding it.
+// storage type, advanced by a HIP graph of persistent step launches between a
+// tick-begin and a tick-end kernel: K single-step launches per storage type,
+// or, for a two-step variant, ceil(K / 2) two-step launches and one
+// single-step tail launch (its own tile table, tail_variant) that takes the
+// last step of members with an odd step count this tick.  The graph reads the
+// tables from device memory, so members can change between replays without
+// rebuilding it.
 struct BatchEngine {
   hipStream_t stream = nullptr;
   int K = 1, cap_inst = 0;
   int cap_items[kNumStorages] = {}, variant[kNumStorages] = {-1, -1, -1},
       grid[kNumStorages] = {}, nitems[kNumStorages] = {};
+  // tail launches of two-step storage types (capacity 0 otherwise)
+  int cap_titems[kNumStorages] = {}, tail_variant[kNumStorages] = {-1, -1, -1},
+      tgrid[kNumStorages] = {};
   InstDesc* d_desc = nullptr;
   // Grid sized to the resident capacity, looping over the items (needed when
   // the item count changes between replays), instead of one workgroup per item.
   bool persistent = false;
   int* d_nitems[kNumStorages] = {};
   TileItem* d_items[kNumStorages] = {};
+  int* d_tnitems[kNumStorages] = {};
+  TileItem* d_titems[kNumStorages] = {};
   // pinned staging of the tables, two sets used in turn (stage = next set)
   InstDesc* h_desc[2] = {};
   TileItem* h_items[kNumStorages][2] = {};
+  TileItem* h_titems[kNumStorages][2] = {};
   hipEvent_t staged[2] = {};
   bool staged_pending[2] = {};
   int stage = 0;
@@ -109,10 +119,15 @@ struct BatchEngine {
   hipGraphExec_t exec = nullptr;
   std::vector<lbm_ctx*> members;
 
-  static size_t work_bytes(int cap_inst, const int cap_items[kNumStorages], int K);
+  // cap_titems: tail tile-table capacities (0 for single-step storage types).
+  static size_t work_bytes(int cap_inst, const int cap_items[kNumStorages],
+                           const int cap_titems[kNumStorages], int K);
   lbm_status init(hipStream_t st, int steps_per_tick, int cap_inst,
-                  const int cap_items[kNumStorages], const int variants[kNumStorages], void* work,
-                  size_t wbytes);
+                  const int cap_items[kNumStorages], const int cap_titems[kNumStorages],
+                  const int variants[kNumStorages], void* work, size_t wbytes);
+  bool two_step(int storage) const {
+    return variant[storage] >= 0 && step_variant(variant[storage]).steps == 2;
+  }
   // Tile used for every member instead of the members' own (-1: none).
   int tile_override = -1;
   int row_override = -1;  // band height index for every member (-1: the member's own)
@@ -136,7 +151,12 @@ lbm_status create_ctx(const lbm_params* p, void* popA, void* popB, size_t pop_by
                       size_t work_bytes, void* hip_stream, bool standalone, lbm_ctx** out);
 lbm_status init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip,
                          bool sync);
-int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override);
+// tail: the items of the tail launch of a two-step variant.
+int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override,
+                bool tail = false);
+// Single-step shape that takes the odd last step of a tick of a two-step
+// variant: strips of kSeriesThreads x 1 cell, 2 rows in flight.
+int tail_variant_for(int variant);
 
 }  // namespace sclbm
 

@@ -398,7 +398,7 @@ void lbm_server::run() {
           const int64_t k = std::min<int64_t>(opts.steps_per_tick, s.left);
           s.left -= k;
           s.ctx->steps += k;
-          s.ctx->parity = (int)((s.ctx->parity + k) & 1);
+          s.ctx->parity = (int)((s.ctx->parity + tick_flips(k, eng.two_step(s.ctx->p.storage))) & 1);
         }
       }
       if (r != LBM_OK) {
@@ -474,16 +474,20 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
   // Engine workspace lives at the top of the pool.
   size_t eng_bytes = 0;
   if (!opts->fake_executor && opts->policy == LBM_POLICY_CONTINUOUS) {
-    // Strip variants, valid for every request width: 256-column strips suit
+    // Strip variants, valid for every request width: 256-thread strips suit
     // the range of request sizes (64 .. 2048 columns) better than wider ones.
-    const int v = find_variant(256, 1, 2, 0);
+    // FP32 takes two steps per launch (a tail launch takes the odd last step
+    // of a tick); FP16 storage one.
+    const int v = find_variant(256, 1, 1, 0, 2);
     const int sw = tile_width(v * kNumRows);
     const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
                                           1u << 22);
     const int cap_items[kNumStorages] = {per, per, per};
+    const int cap_titems[kNumStorages] = {per, 0, 0};
     const int v16 = find_variant(256, 2, 1, 0);
     const int variants[kNumStorages] = {v, v16, v16};
-    eng_bytes = align_up(BatchEngine::work_bytes(opts->max_slots, cap_items, opts->steps_per_tick), 256);
+    eng_bytes = align_up(
+        BatchEngine::work_bytes(opts->max_slots, cap_items, cap_titems, opts->steps_per_tick), 256);
     if (eng_bytes >= pool_bytes / 2) {
       delete s;
       return fail(LBM_ENOMEM, "pool too small for the batch tables");
@@ -493,7 +497,7 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
     // round-robin, which balances only items of similar size.
     s->eng.row_override = row_choice(8);
     lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, cap_items,
-                               variants, s->pool + pool_bytes - eng_bytes, eng_bytes);
+                               cap_titems, variants, s->pool + pool_bytes - eng_bytes, eng_bytes);
     if (r != LBM_OK) {
       s->eng.destroy();
       delete s;

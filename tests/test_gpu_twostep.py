@@ -111,8 +111,9 @@ def test_series_with_two_step_tile_is_unchanged(storage):
 
 
 def test_batch_member_with_two_step_tile():
-    """Batches take one step per launch: a member whose own tile takes two runs
-    with a single-step shape inside the batch, bitwise as alone."""
+    """A batch whose widest member runs a two-step shape takes two steps per
+    launch, plus a single-step tail launch for the odd last step of a tick:
+    bitwise as alone."""
     L = lbm()
     mk = [lambda: L.Simulation(120, 64, -5.0, 1.0).init_droplets([(50, 30, 14)], seed=5),
           lambda: L.Simulation(96, 96, -5.5, 0.9, L.LBM_F16_CELL).init_droplets([(40, 40, 15)], seed=6)]
@@ -127,5 +128,35 @@ def test_batch_member_with_two_step_tile():
         s.step(13)
     for a, s in zip(batch, solo):
         assert a.steps == s.steps == 13
+        assert np.array_equal(to_np(a.get_state()), to_np(s.get_state()))
+    bt.close()
+
+
+@pytest.mark.parametrize("K", [1, 2, 5, 8])
+def test_two_step_batch_matches_single_step_runs(K):
+    """Odd and even steps per graph, step counts split over calls (7 + 10),
+    three storage types in one batch; every member bitwise equal to a
+    single-step run of its own."""
+    L = lbm()
+    specs = [(130, 70, L.LBM_F32, 0.0), (64, 48, L.LBM_F16_SHIFTED, 1.0),
+             (90, 90, L.LBM_F16_CELL, 0.0), (300, 40, L.LBM_F32, 0.0)]
+    def make(i, nx, ny, st, r0):
+        return L.Simulation(nx, ny, -5.5, 0.9, st, r0).init_droplets([(nx / 2, ny / 2, ny / 4)],
+                                                                      seed=10 + i)
+    batch = [make(i, *sp) for i, sp in enumerate(specs)]
+    solo = [make(i, *sp) for i, sp in enumerate(specs)]
+    two = next(t["id"] for t in L.tiles() if t["steps"] == 2 and t["threads"] == 128
+               and t["rows"] == 4)
+    for s in batch:
+        s.set_tile(two)
+    for s in solo:
+        s.set_tile(_strip_tile())
+    bt = L.Batch(batch, steps_per_graph=K)
+    bt.step(7)
+    bt.step(10)
+    for s in solo:
+        s.step(17)
+    for a, s in zip(batch, solo):
+        assert a.steps == 17
         assert np.array_equal(to_np(a.get_state()), to_np(s.get_state()))
     bt.close()
