@@ -18,6 +18,53 @@
 
 namespace sclbm {
 
+// ============================================================== FP64 diagnostics per cell
+
+// FP64 density: the widened populations summed in index order.
+__device__ __forceinline__ double density64(const float (&f)[10]) {
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) r += (double)f[i];
+  return r;
+}
+
+// Accumulators of the diagnostics: mass, mom_x, mom_y, bad cells, cells above
+// the threshold, max |grad rho|, sum |grad rho|, sum |grad rho|^2, rho max, min.
+__device__ __forceinline__ void diag_zero(double (&acc)[10]) {
+#pragma unroll
+  for (int q = 0; q < 10; ++q) acc[q] = 0.0;
+  acc[8] = -INFINITY;
+  acc[9] = INFINITY;
+}
+
+// Diagnostics of one cell (its pre-collision populations f; FP64 rho of the
+// rows below, at and above it in dn, md, up, column c): Eq. (16) with
+// periodic wrap, threshold of Eq. (9) strict.
+__device__ __forceinline__ void diag_cell(double (&acc)[10], const float (&f)[10], int c,
+                                          const double* dn, const double* md, const double* up) {
+  bool fin = true;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fin = fin && isfinite(f[i]);
+  const double r = md[c];
+  const double jx = ((double)f[1] - (double)f[3]) + ((double)f[5] - (double)f[6]) +
+                    ((double)f[8] - (double)f[7]);
+  const double jy = ((double)f[2] - (double)f[4]) + ((double)f[5] - (double)f[8]) +
+                    ((double)f[6] - (double)f[7]);
+  const double gx = (md[c + 1] - md[c - 1]) / 2.0;
+  const double gy = (up[c] - dn[c]) / 2.0;
+  const double g = sqrt(gx * gx + gy * gy);
+  acc[0] += r;
+  acc[1] += jx;
+  acc[2] += jy;
+  if (!fin || !(r > 0.0)) acc[3] += 1.0;
+  if (g > 0.01) acc[4] += 1.0;
+  acc[5] = fmax(acc[5], g);
+  acc[6] += g;
+  acc[7] += g * g;
+  acc[8] = fmax(acc[8], r);
+  acc[9] = fmin(acc[9], r);
+}
+
 // ============================================================== step kernel
 //
 // A workgroup of NT threads owns a strip of SW = NT * CPT columns (thread t
@@ -200,47 +247,13 @@ struct Strip {
     }
   }
 
-  // FP64 density: the widened populations summed in index order.
   __device__ __forceinline__ static double density64(const float (&f)[10]) {
-    double r = 0.0;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) r += (double)f[i];
-    return r;
+    return sclbm::density64(f);
   }
-
-  __device__ __forceinline__ void diag_zero() {
-#pragma unroll
-    for (int q = 0; q < 10; ++q) acc[q] = 0.0;
-    acc[8] = -INFINITY;
-    acc[9] = INFINITY;
-  }
-
-  // Diagnostics of one cell of position r (its pre-collision populations f,
-  // FP64 rho of rows r-1, r, r+1 in the ring): Eq. (16) with periodic wrap,
-  // threshold of Eq. (9) strict.
+  __device__ __forceinline__ void diag_zero() { sclbm::diag_zero(acc); }
   __device__ __forceinline__ void diag_cell(const float (&f)[10], int c, const double* dn,
                                             const double* md, const double* up) {
-    bool fin = true;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) fin = fin && isfinite(f[i]);
-    const double r = md[c];
-    const double jx = ((double)f[1] - (double)f[3]) + ((double)f[5] - (double)f[6]) +
-                      ((double)f[8] - (double)f[7]);
-    const double jy = ((double)f[2] - (double)f[4]) + ((double)f[5] - (double)f[8]) +
-                      ((double)f[6] - (double)f[7]);
-    const double gx = (md[c + 1] - md[c - 1]) / 2.0;
-    const double gy = (up[c] - dn[c]) / 2.0;
-    const double g = sqrt(gx * gx + gy * gy);
-    acc[0] += r;
-    acc[1] += jx;
-    acc[2] += jy;
-    if (!fin || !(r > 0.0)) acc[3] += 1.0;
-    if (g > 0.01) acc[4] += 1.0;
-    acc[5] = fmax(acc[5], g);
-    acc[6] += g;
-    acc[7] += g * g;
-    acc[8] = fmax(acc[8], r);
-    acc[9] = fmin(acc[9], r);
+    sclbm::diag_cell(acc, f, c, dn, md, up);
   }
 
   // Collide the row at march position r (psi of positions r-1, r, r+1 already
@@ -976,10 +989,16 @@ __device__ __forceinline__ void unrolled(std::integer_sequence<int, I...>, Fn&& 
   (fn(std::integral_constant<int, I>{}), ...);
 }
 
-template <class S, int NT, int PF>
-__global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs,
-                                              const TileItem* __restrict__ items,
-                                              const int* __restrict__ nitems_p, int sub) {
+// The march of the two-step kernels.  DIAG = true also accumulates the FP64
+// diagnostics of the state the launch reads (the cells the workgroup owns,
+// from the populations pulled for the first step, per cell in the arithmetic
+// of the separate pass; FP64 rho goes through a third LDS ring) and writes
+// one partial record per item.
+template <class S, int NT, int PF, bool DIAG>
+__device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ descs,
+                                               const TileItem* __restrict__ items,
+                                               const int* __restrict__ nitems_p, int sub,
+                                               double* __restrict__ partials) {
   static_assert(PF == 1 || PF == 2, "one or two rows of loads in flight");
   using F = Fused2<S, NT, PF>;
   using T = typename S::T;
@@ -992,13 +1011,17 @@ __global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs
   constexpr bool kInPlace = std::is_same<S, StoreF32>::value;
   constexpr int NR = kInPlace ? PF + 2 : PF + 1;
   // With U a multiple of 3 the LDS ring slots are constants too (not taken
-  // for per-cell-shift storage, whose longer period needs too many registers).
-  constexpr int U = ((NR == 2 && !S::kCellShift) || NR == 3) ? 6 : (NR % 2 == 0 ? NR : 2 * NR);
+  // for per-cell-shift storage and the diagnostics variant, whose longer
+  // period needs too many registers).
+  constexpr int U = !DIAG && ((NR == 2 && !S::kCellShift) || NR == 3)
+                        ? 6
+                        : (NR % 2 == 0 ? NR : 2 * NR);
   constexpr bool kFixedRing = U % 3 == 0;
   constexpr int NF = kInPlace ? NR : 2;  // FP32 rows of the first step
   __shared__ float psa[3][NT];    // psi(t) rows
   __shared__ float fs[3][9][NT];  // f*(t + 1) rows, as read back from storage
   __shared__ float psb[3][NT];    // psi(t + 1) rows
+  __shared__ double rr[DIAG ? 3 : 1][DIAG ? NT : 1];  // FP64 rho(t) rows
   const int nitems = *nitems_p;
   const int t = threadIdx.x;
   const bool stage_a = t >= 1 && t <= NT - 2;
@@ -1006,9 +1029,13 @@ __global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs
   // Lanes that store nothing still run the last collision (on clamped ring
   // columns) so that the row's stores need no branch.
   const int tf = min(max(t, 1), NT - 2);
+  const int op[10] = {0, 0, 0, 0, 0, 1, 0, 0, 1, 2};  // sum, max, min
+  (void)op;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
+    double acc[10];
+    if constexpr (DIAG) diag_zero(acc);
     if (pair_runs(dp, sub)) {
       F s;
       s.setup(dp, ti, sub);
@@ -1053,7 +1080,12 @@ __global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs
         else
           s.decode(raw[kd], fa_c);
         psa[ring(3)][t] = psi_of(fa_c[9]);
+        if constexpr (DIAG) rr[ring(3)][t] = density64(fa_c);
         __syncthreads();
+        if constexpr (DIAG) {  // the state read, row j + 2, before its collision
+          if ((unsigned)(j + 2) < (unsigned)h && s.out)
+            diag_cell(acc, fa_p, t, rr[ring(2 + below)], rr[ring(2)], rr[ring(2 - below)]);
+        }
         if ((!kLead || j >= -4) && stage_a) {  // row j + 2
           float Fx, Fy;
           ring_force(psa[ring(2 + below)], psa[ring(2)], psa[ring(2 - below)], t, s.G, Fx, Fy);
@@ -1108,8 +1140,32 @@ __global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs
       else
         march(std::false_type{});
     }
+    if constexpr (DIAG) {
+      block_reduce<10>(acc, op);
+      if (threadIdx.x == 0)
+        for (int q = 0; q < 10; ++q) partials[(size_t)it * kPartialStride + q] = acc[q];
+    }
     __syncthreads();  // the next item reuses the rings
   }
+}
+
+template <class S, int NT, int PF>
+__global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs,
+                                              const TileItem* __restrict__ items,
+                                              const int* __restrict__ nitems_p, int sub) {
+  two_step_march<S, NT, PF, false>(descs, items, nitems_p, sub, nullptr);
+}
+
+// Two steps that also record the diagnostics of the state they advance (one
+// partial record of kPartialStride doubles per item, folded afterwards).
+constexpr int kDiag2Threads = 256;
+template <class S>
+__global__ __launch_bounds__(kDiag2Threads) void k_step2_diag(const InstDesc* __restrict__ descs,
+                                                              const TileItem* __restrict__ items,
+                                                              const int* __restrict__ nitems_p,
+                                                              int sub,
+                                                              double* __restrict__ partials) {
+  two_step_march<S, kDiag2Threads, 1, true>(descs, items, nitems_p, sub, partials);
 }
 
 // ============================================================== batched ticks
@@ -1763,6 +1819,21 @@ hipError_t launch_step_diag(int storage, const InstDesc* descs, const TileItem* 
     using S = decltype(tag);
     hipLaunchKernelGGL(k_step_diag<S>, dim3(grid), dim3(kDiagThreads), 0, st, descs, items, nitems,
                        sub, partials);
+    return hipGetLastError();
+  });
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, grid,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_step2_diag(int storage, const InstDesc* descs, const TileItem* items,
+                             const int* nitems, int grid, int sub, double* partials, double* out,
+                             hipStream_t st) {
+  const hipError_t e = with_storage(storage, [&](auto tag) {
+    using S = decltype(tag);
+    hipLaunchKernelGGL(k_step2_diag<S>, dim3(grid), dim3(kDiag2Threads), 0, st, descs, items,
+                       nitems, sub, partials);
     return hipGetLastError();
   });
   if (e != hipSuccess) return e;

@@ -79,6 +79,13 @@ constexpr int kSeriesChunk = 256;  // records kept on the device between copies
 hipError_t launch_step_diag(int storage, const InstDesc* descs, const TileItem* items,
                             const int* nitems, int grid, int sub, double* partials,
                             double* out, hipStream_t st);
+// Two steps with the diagnostics of the state they advance: two-step tile of
+// kSeriesThreads threads, 1 row in flight (kSeries2Rows-row bands); `grid` =
+// number of items (one partial record each).
+constexpr int kSeries2Rows = 16;
+hipError_t launch_step2_diag(int storage, const InstDesc* descs, const TileItem* items,
+                             const int* nitems, int grid, int sub, double* partials, double* out,
+                             hipStream_t st);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t st);
 
 }  // namespace sclbm

@@ -75,12 +75,21 @@ WorkLayout work_layout(int nx, int ny) {
   // the series tile: kSeriesThreads-wide strips, row index 0 (8-row bands)
   w.series_items = ((nx + kSeriesThreads - 1) / kSeriesThreads) *
                    ((ny + kRowChoices[0] - 1) / kRowChoices[0]);
+  // and the two-step recording tile: kSeriesThreads - kFusedHalo columns,
+  // kSeries2Rows-row bands
+  const int w2 = kSeriesThreads - kFusedHalo;
+  w.series2_items = ((nx + w2 - 1) / w2) * ((ny + kSeries2Rows - 1) / kSeries2Rows);
   w.s_nitems = o;
   o += 256;
   w.s_items = o;
   o = align_up(o + (size_t)w.series_items * sizeof(TileItem), 256);
+  w.s2_nitems = o;
+  o += 256;
+  w.s2_items = o;
+  o = align_up(o + (size_t)w.series2_items * sizeof(TileItem), 256);
   w.s_partials = o;
-  o = align_up(o + (size_t)w.series_items * kPartialStride * sizeof(double), 256);
+  o = align_up(o + (size_t)std::max(w.series_items, w.series2_items) * kPartialStride *
+                       sizeof(double), 256);
   w.s_records = o;
   o += (size_t)kSeriesChunk * 16 * sizeof(double);
   w.total = o;
@@ -364,22 +373,33 @@ lbm_metrics lbm_ctx::metrics_from_raw(const double* r, int64_t step) const {
   return m;
 }
 
-// The series tile table (built on first use): strips of kSeriesThreads x 1
-// cell, 2 rows in flight, 8-row bands.  Also the single-step tile of runs
-// whose own tile takes two steps per launch.
+// The series tile tables (built on first use).  Single-step: strips of
+// kSeriesThreads x 1 cell, 2 rows in flight, 8-row bands (also the
+// single-step tile of runs whose own tile takes two steps per launch).
+// Two-step: kSeriesThreads threads, 1 row in flight, kSeries2Rows-row bands.
 lbm_status lbm_ctx::series_tiles() {
   if (series_nitems > 0) return LBM_OK;
-  const int k = find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + 0;
-  std::vector<TileItem> items;
-  make_items(p.nx, p.ny, p.storage, k, 0, items);
-  items = xcd_order(items);
-  if ((int)items.size() > lay.series_items) return fail(LBM_EINVAL, "series tile table overflow");
-  const int ni = (int)items.size();
-  SCLBM_HIP(hipMemcpyAsync(d_sitems, items.data(), items.size() * sizeof(TileItem),
-                           hipMemcpyHostToDevice, stream));
-  SCLBM_HIP(hipMemcpyAsync(d_snitems, &ni, sizeof(int), hipMemcpyHostToDevice, stream));
+  auto build = [&](int k, int cap, TileItem* d_it, int* d_n, int* count) -> lbm_status {
+    std::vector<TileItem> items;
+    make_items(p.nx, p.ny, p.storage, k, 0, items);
+    items = xcd_order(items);
+    if ((int)items.size() > cap) return fail(LBM_EINVAL, "series tile table overflow");
+    *count = (int)items.size();
+    SCLBM_HIP(hipMemcpyAsync(d_it, items.data(), items.size() * sizeof(TileItem),
+                             hipMemcpyHostToDevice, stream));
+    SCLBM_HIP(hipMemcpyAsync(d_n, count, sizeof(int), hipMemcpyHostToDevice, stream));
+    return LBM_OK;
+  };
+  int n1 = 0, n2 = 0;
+  lbm_status r = build(find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + row_choice(8),
+                       lay.series_items, d_sitems, d_snitems, &n1);
+  if (r == LBM_OK)
+    r = build(find_variant(kSeriesThreads, 1, 1, 0, 2) * kNumRows + row_choice(kSeries2Rows),
+              lay.series2_items, d_s2items, d_s2nitems, &n2);
+  if (r != LBM_OK) return r;
   SCLBM_HIP(hipStreamSynchronize(stream));
-  series_nitems = ni;
+  series_nitems = n1;
+  series2_nitems = n2;
   return LBM_OK;
 }
 
@@ -428,17 +448,26 @@ lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int3
     return LBM_OK;
   };
   for (int64_t j = 0; j < n;) {
-    // one step that records the metrics, then the plain steps up to the next
-    SCLBM_HIP(launch_step_diag(p.storage, d_desc, d_sitems, d_snitems, series_nitems, parity,
-                               d_spartials, d_srecords + (size_t)pending * 16, stream));
+    // The step that records the metrics, then the plain steps up to the next
+    // record.  With at least one plain step to follow, the recording launch
+    // takes two steps.
+    const int64_t plain = std::min<int64_t>(every - 1, n - j - 1);
+    double* rec = d_srecords + (size_t)pending * 16;
+    if (plain >= 1) {
+      SCLBM_HIP(launch_step2_diag(p.storage, d_desc, d_s2items, d_s2nitems, series2_nitems,
+                                  parity, d_spartials, rec, stream));
+      steps += 2;
+    } else {
+      SCLBM_HIP(launch_step_diag(p.storage, d_desc, d_sitems, d_snitems, series_nitems, parity,
+                                 d_spartials, rec, stream));
+      steps += 1;
+    }
     parity ^= 1;
-    steps += 1;
     if (++pending == kSeriesChunk) {
       const lbm_status s = flush();
       if (s != LBM_OK) return s;
     }
-    const int64_t plain = std::min<int64_t>(every - 1, n - j - 1);
-    const lbm_status s = advance(plain);
+    const lbm_status s = advance(plain >= 1 ? plain - 1 : 0);
     if (s != LBM_OK) return s;
     j += 1 + plain;
   }
@@ -810,6 +839,8 @@ lbm_status sclbm::create_ctx(const lbm_params* p, void* popA, void* popB, size_t
   c->d_result = reinterpret_cast<double*>(w + lay.result);
   c->d_snitems = reinterpret_cast<int*>(w + lay.s_nitems);
   c->d_sitems = reinterpret_cast<TileItem*>(w + lay.s_items);
+  c->d_s2nitems = reinterpret_cast<int*>(w + lay.s2_nitems);
+  c->d_s2items = reinterpret_cast<TileItem*>(w + lay.s2_items);
   c->d_spartials = reinterpret_cast<double*>(w + lay.s_partials);
   c->d_srecords = reinterpret_cast<double*>(w + lay.s_records);
   c->arch = device_arch();

@@ -66,10 +66,11 @@ std::vector<TileItem> xcd_order(const std::vector<TileItem>& items);
 // Workspace layout of a single run.
 struct WorkLayout {
   size_t desc, nitems, items, partials, result;
-  // metric series: its own tile table, one partial record per item, records
-  size_t s_nitems, s_items, s_partials, s_records;
+  // metric series: its tile tables (single-step and two-step recording
+  // steps), one partial record per item, records
+  size_t s_nitems, s_items, s2_nitems, s2_items, s_partials, s_records;
   size_t total;
-  int max_items, series_items;
+  int max_items, series_items, series2_items;
 };
 WorkLayout work_layout(int nx, int ny);
 
@@ -178,8 +179,11 @@ struct lbm_ctx {
   double* d_partials = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;  // pinned
-  int* d_snitems = nullptr;     // metric-series tile table (built on first use)
+  int* d_snitems = nullptr;     // metric-series tile tables (built on first use)
   sclbm::TileItem* d_sitems = nullptr;
+  int* d_s2nitems = nullptr;
+  sclbm::TileItem* d_s2items = nullptr;
+  int series2_nitems = 0;
   double* d_spartials = nullptr;
   double* d_srecords = nullptr;
   double* h_series = nullptr;  // pinned, kSeriesChunk records
