@@ -108,7 +108,7 @@ def run_main(args, torch, lbm, inputs):
         if args.tile >= 0:
             sim.set_tile(args.tile)
         elif not args.no_autotune:
-            sim.autotune(reps=4)
+            sim.autotune(reps=8)
         rho = torch.empty((N, N), dtype=torch.float32, device="cuda")
         ux = torch.empty_like(rho)
         uy = torch.empty_like(rho)
@@ -292,9 +292,12 @@ def run_sweep(args, torch, lbm, inputs):
         unstable = sum(1 for s in sims if not s.metrics()["finite"])
         lu = 256.0 * 256 * len(sims) * args.sweep_steps
         bpu = BYTES_F32 if storage == lbm.LBM_F32 else BYTES_F16
+        spl = lbm.tiles()[tile]["steps"] if tile >= 0 else 1
+        # algorithmic bytes: each launch reads and writes every population once
         res[name] = {"mlups": lu / wall / 1e6, "gpu_mlups": lu / (ms * 1e-3) / 1e6,
-                     "achieved_gbs": lu * bpu / (ms * 1e-3) / 1e9, "instances": len(sims),
-                     "steps": args.sweep_steps, "unstable_instances": unstable, "tile": tile}
+                     "achieved_gbs": lu * bpu / spl / (ms * 1e-3) / 1e9, "steps_per_launch": spl,
+                     "instances": len(sims), "steps": args.sweep_steps,
+                     "unstable_instances": unstable, "tile": tile}
         log(f"[sweep {name}] {res[name]['gpu_mlups']:.0f} MLUPS, {unstable} unstable")
         for s in sims:
             s.close()
