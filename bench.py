@@ -76,7 +76,7 @@ def kernel_name(lbm, tile: int, storage: int) -> str:
     t = lbm.tiles()[tile]
     st = {lbm.LBM_F32: "StoreF32", lbm.LBM_F16_SHIFTED: "StoreF16S", lbm.LBM_F16_CELL: "StoreF16C"}[storage]
     if t["steps"] == 2:
-        return f"k_step2<{st}, {t['threads']}, {t['prefetch']}>"
+        return f"k_step2<{st}, {t['threads']}, {t['prefetch']}, {t['width']}>"
     if t["paired"]:
         return f"k_step_pair<{st}, {t['threads'] // 64}, {t['prefetch']}>"
     return f"k_step<{st}, {t['threads']}, {t['cells']}, {t['prefetch']}>"

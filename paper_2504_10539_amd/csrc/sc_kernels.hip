@@ -800,10 +800,10 @@ struct RawCell {
   typename S::T q[9];  // reference densities (per-cell-shift storage)
 };
 
-template <class S, int NT, int PF>
+template <class S, int NT, int PF, int W>
 struct Fused2 {
+  static_assert(W <= NT - kFusedHalo, "three halo lanes on each side");
   using T = typename S::T;
-  static constexpr int W = NT - 6;
 
   uint64_t src, dst;
   float sh[9];
@@ -994,13 +994,13 @@ __device__ __forceinline__ void unrolled(std::integer_sequence<int, I...>, Fn&& 
 // from the populations pulled for the first step, per cell in the arithmetic
 // of the separate pass; FP64 rho goes through a third LDS ring) and writes
 // one partial record per item.
-template <class S, int NT, int PF, bool DIAG>
+template <class S, int NT, int PF, int W, bool DIAG>
 __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ descs,
                                                const TileItem* __restrict__ items,
                                                const int* __restrict__ nitems_p, int sub,
                                                double* __restrict__ partials) {
   static_assert(PF == 1 || PF == 2, "one or two rows of loads in flight");
-  using F = Fused2<S, NT, PF>;
+  using F = Fused2<S, NT, PF, W>;
   using T = typename S::T;
   // FP32 rows are loaded straight into the registers they are collided in:
   // a slot lives from its loads to the first collision, PF + 2 positions.
@@ -1149,11 +1149,14 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
   }
 }
 
-template <class S, int NT, int PF>
+// W output columns per workgroup (at most NT - kFusedHalo): with W a
+// multiple of 16, every strip of an FP32 row starts and ends on a 64-byte
+// boundary, so no write granule is shared by two workgroups.
+template <class S, int NT, int PF, int W>
 __global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs,
                                               const TileItem* __restrict__ items,
                                               const int* __restrict__ nitems_p, int sub) {
-  two_step_march<S, NT, PF, false>(descs, items, nitems_p, sub, nullptr);
+  two_step_march<S, NT, PF, W, false>(descs, items, nitems_p, sub, nullptr);
 }
 
 // Two steps that also record the diagnostics of the state they advance (one
@@ -1165,7 +1168,8 @@ __global__ __launch_bounds__(kDiag2Threads) void k_step2_diag(const InstDesc* __
                                                               const int* __restrict__ nitems_p,
                                                               int sub,
                                                               double* __restrict__ partials) {
-  two_step_march<S, kDiag2Threads, 1, true>(descs, items, nitems_p, sub, partials);
+  two_step_march<S, kDiag2Threads, 1, kDiag2Threads - kFusedHalo, true>(descs, items, nitems_p,
+                                                                       sub, partials);
 }
 
 // ============================================================== batched ticks
@@ -1587,16 +1591,17 @@ const void* step_fn_t() {
   return reinterpret_cast<const void*>(&k_step<S, NT, CPT, PF>);
 }
 
-template <class S, int NT, int PF>
+template <class S, int NT, int PF, int W>
 hipError_t launch_fused_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                           int grid, int sub, hipStream_t st) {
-  hipLaunchKernelGGL((k_step2<S, NT, PF>), dim3(grid), dim3(NT), 0, st, descs, items, nitems, sub);
+  hipLaunchKernelGGL((k_step2<S, NT, PF, W>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
+                     sub);
   return hipGetLastError();
 }
 
-template <class S, int NT, int PF>
+template <class S, int NT, int PF, int W>
 const void* fused_fn_t() {
-  return reinterpret_cast<const void*>(&k_step2<S, NT, PF>);
+  return reinterpret_cast<const void*>(&k_step2<S, NT, PF, W>);
 }
 
 template <class S, int NW, int PF>
@@ -1627,17 +1632,21 @@ using StepFn = const void* (*)();
 #define SCLBM_PAIR_VARIANTS(X) X(1, 1) X(1, 2) X(2, 1) X(2, 2) X(4, 1) X(4, 2)
 
 // Two-step variants (threads, rows in flight).
-#define SCLBM_FUSED_VARIANTS(X) X(128, 1) X(256, 1) X(256, 2) X(512, 1) X(512, 2)
+// Two-step variants (threads, rows in flight, output columns): the widest
+// strips, and strips of a multiple of 16 columns (64-byte aligned in FP32).
+#define SCLBM_FUSED_VARIANTS(X)                                                               \
+  X(128, 1, 122) X(256, 1, 250) X(256, 2, 250) X(512, 1, 506) X(512, 2, 506) X(128, 1, 112) \
+  X(256, 1, 240) X(256, 2, 240) X(512, 1, 496)
 
-#define SCLBM_AS_VARIANT(NT, CPT, PF) StepVariant{NT, CPT, PF, 0, 1},
+#define SCLBM_AS_VARIANT(NT, CPT, PF) StepVariant{NT, CPT, PF, 0, 1, 0},
 #define SCLBM_AS_LAUNCH(NT, CPT, PF) launch_step_t<S, NT, CPT, PF>,
 #define SCLBM_AS_FN(NT, CPT, PF) step_fn_t<S, NT, CPT, PF>,
-#define SCLBM_PAIR_AS_VARIANT(NW, PF) StepVariant{64 * NW, 2, PF, 1, 1},
+#define SCLBM_PAIR_AS_VARIANT(NW, PF) StepVariant{64 * NW, 2, PF, 1, 1, 0},
 #define SCLBM_PAIR_AS_LAUNCH(NW, PF) launch_pair_t<S, NW, PF>,
 #define SCLBM_PAIR_AS_FN(NW, PF) pair_fn_t<S, NW, PF>,
-#define SCLBM_FUSED_AS_VARIANT(NT, PF) StepVariant{NT, 1, PF, 0, 2},
-#define SCLBM_FUSED_AS_LAUNCH(NT, PF) launch_fused_t<S, NT, PF>,
-#define SCLBM_FUSED_AS_FN(NT, PF) fused_fn_t<S, NT, PF>,
+#define SCLBM_FUSED_AS_VARIANT(NT, PF, W) StepVariant{NT, 1, PF, 0, 2, W},
+#define SCLBM_FUSED_AS_LAUNCH(NT, PF, W) launch_fused_t<S, NT, PF, W>,
+#define SCLBM_FUSED_AS_FN(NT, PF, W) fused_fn_t<S, NT, PF, W>,
 constexpr StepVariant kVariants[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_VARIANT)
                                          SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_VARIANT)
                                              SCLBM_FUSED_VARIANTS(SCLBM_FUSED_AS_VARIANT)};

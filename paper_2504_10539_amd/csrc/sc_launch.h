@@ -13,12 +13,12 @@ namespace sclbm {
 // rows of loads in flight.  Marching-strip variants (paired = 0) cover
 // NT * CPT columns per workgroup; paired-column variants (paired = 1, CPT = 2)
 // cover kPairColumns per wavefront and need an even nx >= 128.  Two-step
-// variants (steps = 2, CPT = 1) advance NT - kFusedHalo columns by two time
-// steps per launch.
+// variants (steps = 2, CPT = 1) advance `width` <= NT - kFusedHalo columns by
+// two time steps per launch (0 for the other kinds).
 struct StepVariant {
-  int threads, cells, prefetch, paired, steps;
+  int threads, cells, prefetch, paired, steps, width;
 };
-constexpr int kNumVariants = 25;
+constexpr int kNumVariants = 29;
 constexpr int kFusedHalo = 6;
 constexpr int kPairColumns = 124;
 constexpr int kPairMinNx = 128;

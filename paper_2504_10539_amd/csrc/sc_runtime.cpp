@@ -174,14 +174,15 @@ int default_strip_tile(const lbm_params& p) {
 int default_tile(const lbm_params& p) {
   const size_t cells = (size_t)p.nx * (size_t)p.ny;
   // From a million cells up, two steps per launch wherever that measured
-  // faster: FP32 (256 threads from 4M cells with 8-row bands, else 128 with
-  // 4-row bands); FP16-shifted (from 16M cells 256 threads, 2 rows in
-  // flight, balanced bands; else 128 threads, 16-row bands from 4M cells,
-  // 4-row from 1M); FP16 shifted per cell from 16M cells (as FP16-shifted).
-  if (p.storage == LBM_F32 && cells >= (1u << 20)) {
-    const bool big = cells >= (4u << 20);
-    return find_variant(big ? 256 : 128, 1, 1, 0, 2) * kNumRows + row_choice(big ? 8 : 4);
-  }
+  // faster: FP32 (from 4M cells 256 threads writing 240 columns, 8-row
+  // bands; else 128 threads with 4-row bands); FP16-shifted (from 16M cells
+  // 256 threads, 2 rows in flight, balanced bands; else 128 threads, 16-row
+  // bands from 4M cells, 4-row from 1M); FP16 shifted per cell from 16M cells
+  // (as FP16-shifted).
+  if (p.storage == LBM_F32 && cells >= (4u << 20))
+    return find_variant(256, 1, 1, 0, 2, 240) * kNumRows + row_choice(8);
+  if (p.storage == LBM_F32 && cells >= (1u << 20))
+    return find_variant(128, 1, 1, 0, 2) * kNumRows + row_choice(4);
   if (p.storage == LBM_F16_SHIFTED && cells >= (16u << 20))
     return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
   if (p.storage == LBM_F16_SHIFTED && cells >= (1u << 20))

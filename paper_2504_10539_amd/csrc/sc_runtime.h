@@ -31,17 +31,19 @@ inline int tile_variant(int k) { return k / kNumRows; }
 inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }  // 0: balanced
 inline int tile_width(int k) {
   const StepVariant& v = step_variant(tile_variant(k));
-  if (v.steps == 2) return v.threads - kFusedHalo;
+  if (v.steps == 2) return v.width;
   return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
 }
 // Time steps one launch of tile shape k takes.
 inline int tile_steps(int k) { return step_variant(tile_variant(k)).steps; }
 // Index of the step variant with these parameters (-1 if there is none).
-inline int find_variant(int threads, int cells, int prefetch, int paired, int steps = 1) {
+// width: a two-step variant's output columns (0: the widest).
+inline int find_variant(int threads, int cells, int prefetch, int paired, int steps = 1,
+                        int width = 0) {
   for (int v = 0; v < kNumVariants; ++v) {
     const StepVariant& s = step_variant(v);
     if (s.threads == threads && s.cells == cells && s.prefetch == prefetch && s.paired == paired &&
-        s.steps == steps)
+        s.steps == steps && (width == 0 || s.width == width))
       return v;
   }
   return -1;

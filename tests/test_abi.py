@@ -112,7 +112,9 @@ def test_tile_table(lbm):
     for t in tiles:
         assert t["steps"] in (1, 2)
         if t["steps"] == 2:  # three halo columns on each side of the strip
-            assert not t["paired"] and t["cells"] == 1 and t["width"] == t["threads"] - 6
+            assert not t["paired"] and t["cells"] == 1
+            assert t["width"] == t["threads"] - 6 or (t["width"] < t["threads"] - 6
+                                                      and t["width"] % 16 == 0)
         elif t["paired"]:
             assert t["cells"] == 2 and t["width"] == t["threads"] // 64 * 124
         else:

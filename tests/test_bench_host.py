@@ -29,7 +29,7 @@ def test_kernel_names(lbm):
         f"k_step_pair<StoreF16S, 4, {pair['prefetch']}>"
     two = next(t for t in tiles if t["steps"] == 2 and t["threads"] == 256)
     assert bench.kernel_name(lbm, two["id"], lbm.LBM_F16_CELL) == \
-        f"k_step2<StoreF16C, 256, {two['prefetch']}>"
+        f"k_step2<StoreF16C, 256, {two['prefetch']}, {two['width']}>"
 
 
 def test_launch_figures_count_one_read_and_write_per_launch(lbm):
