@@ -476,9 +476,9 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
   if (!opts->fake_executor && opts->policy == LBM_POLICY_CONTINUOUS) {
     // Strip variants, valid for every request width: 256-thread strips suit
     // the range of request sizes (64 .. 2048 columns) better than wider ones.
-    // FP32 takes two steps per launch (a tail launch takes the odd last step
-    // of a tick); FP16 storage one.
-    const int v = find_variant(256, 1, 1, 0, 2);
+    // FP32 takes two steps per launch on 64-byte-aligned 240-column strips (a
+    // tail launch takes the odd last step of a tick); FP16 storage one.
+    const int v = find_variant(256, 1, 1, 0, 2, 240);
     const int sw = tile_width(v * kNumRows);
     const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
                                           1u << 22);
