@@ -248,6 +248,32 @@ def run_paper_preset(args, torch, lbm):
     return res
 
 
+def run_one_step_reference(args, torch, lbm, inputs):
+    """The best single-step FP32 shape on the same workload (strips of 512
+    threads, 2 rows in flight, 64-row bands), timed over 200 steps: the HBM
+    roofline fraction a kernel that reads and writes every population once per
+    step reaches, beside the two-step kernel's."""
+    N = args.n
+    sim = lbm.Simulation(N, N, args.G, args.tau, lbm.LBM_F32)
+    sim.init_droplets(inputs.many_droplets(N, args.drops, 8, 48, seed=3), seed=3)
+    tile = next(t["id"] for t in lbm.tiles() if t["steps"] == 1 and not t["paired"]
+                and t["threads"] == 512 and t["cells"] == 1 and t["prefetch"] == 2
+                and t["rows"] == 64)
+    sim.set_tile(tile)
+    sim.step(20)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(200)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 200
+    sim.close()
+    gbs = BYTES_F32 * N * N / (ms * 1e-3) / 1e9
+    return {"kernel": kernel_name(lbm, tile, lbm.LBM_F32), "tile": tile,
+            "launch_ms": round(ms, 5), "achieved": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
 def run_copy_reference(torch, lbm):
     n = 2 << 30
     a = torch.empty(n, dtype=torch.uint8, device="cuda")
@@ -422,6 +448,7 @@ def main():
     f32 = main_res["f32"]
     khash = kernel_source_hash()
     copy_gbs = run_copy_reference(torch, lbm)
+    one_step = run_one_step_reference(args, torch, lbm, inputs)
     traffic = traffic_from_profiles(lbm, khash, "f32", args.n, f32["tile"])
     line = {
         "metric": "MLUPS & % HBM roofline (FP32 vs FP16-shifted); batched p50/p99 latency",
@@ -448,6 +475,7 @@ def main():
                      "steps_per_launch": f32["steps_per_launch"],
                      "launch_ms": round(f32["launch_ms"], 5),
                      "over_one_step_roofline": round(f32["over_one_step_roofline"], 4),
+                     "one_step_kernel": one_step,
                      "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
         "f32": f32,
     }

@@ -784,16 +784,17 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
 // Temporal blocking: a workgroup advances its strip of a band by two time
 // steps in one pass, so the populations cross HBM once per two updates.  The
 // post-collision values of the intermediate step never leave the CU: they go
-// through a four-row LDS ring, rounded through the storage form exactly as a
+// through a three-row LDS ring, rounded through the storage form exactly as a
 // store and a load would round them, so the result is bitwise that of two
 // single steps.  Strip slot k (see strip_slot) holds column x0 - 3 + k (mod
 // nx).  Per march row j:
 //   1. pull f(t) of row j + 3 (loads issued PF rows ahead), publish psi(t);
-//   2. collide row j + 2 into the ring (columns x0 - 2 .. x0 + W + 1);
+//   2. collide row j + 2 into the ring (slots 1 .. NT - 2);
 //   3. pull f(t + 1) of row j + 1 from the ring, publish psi(t + 1);
 //   4. collide row j and store it (columns x0 .. x0 + W - 1).
 // One barrier separates each stage from the next.  The band's rows are
-// reached through three halo rows above and below; W = NT - 6 columns.
+// reached through three halo rows above and below; a strip writes W <= NT - 6
+// columns.
 
 template <class S>
 struct RawCell {
