@@ -513,6 +513,13 @@ __device__ __forceinline__ float mix_lo(uint32_t q, float w, uint32_t h) {
   asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(q), "v"(w), "v"(h));
   return r;
 }
+// The same on two halves held in registers of their own (the instruction
+// reads the low 16 bits only, so they need no masking).
+__device__ __forceinline__ float mix_lo(_Float16 q, float w, _Float16 h) {
+  float r;
+  asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel_hi:[1,0,1]" : "=v"(r) : "v"(q), "v"(w), "v"(h));
+  return r;
+}
 __device__ __forceinline__ float mix_hi(uint32_t q, float w, uint32_t h) {
   float r;
   asm("v_fma_mix_f32 %0, %1, %2, %3 op_sel:[1,0,1] op_sel_hi:[1,0,1]"
@@ -918,12 +925,6 @@ struct Fused2 {
     }
   }
 
-  // Bits of a half in the low 16 bits of a word (the mixed-precision FMAs
-  // below read only those).
-  __device__ __forceinline__ static uint32_t bits(T h) {
-    return (uint32_t)__builtin_bit_cast(uint16_t, h);
-  }
-
   // Widening of the pulled values, as the storage type reads them back.  For
   // per-cell-shift storage one mixed-precision FMA per value (rhohat * w_i + h,
   // both halves read directly), equal to StoreF16C::decode.  (The same form
@@ -934,7 +935,7 @@ struct Fused2 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       if constexpr (S::kCellShift)
-        f[i] = mix_lo(bits(r.q[i]), ws[i], bits(r.v[i]));
+        f[i] = mix_lo(r.q[i], ws[i], r.v[i]);
       else
         f[i] = S::load(&r.v[i], sh[i]);
     }
@@ -946,7 +947,7 @@ struct Fused2 {
     const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
     if constexpr (S::kCellShift) {
       const T rh = S::ref(rho);
-      return mix_lo(bits(rh), ws[i], bits(S::encode(v, rh, ws[i])));
+      return mix_lo(rh, ws[i], S::encode(v, rh, ws[i]));
     } else if constexpr (sizeof(T) == 2) {
       const T hv = S::pack(v, sh[i]);
       return S::load(&hv, sh[i]);
