@@ -827,9 +827,13 @@ struct Fused2 {
   static_assert(W <= NT - kFusedHalo, "three halo lanes on each side");
   using T = typename S::T;
 
-  uint64_t src, dst;
+  static_assert(SCLBM_ROW_LAYOUT, "lattice row y keeps its nine population rows together");
+
+  uint64_t src, dst;    // population arrays read and written
+  uint64_t qsrc, qdst;  // their reference-density planes (per-cell shift)
   float sh[9];
   int nx, ny, y0, h, dir, wcols;
+  uint32_t lrow, prow;  // bytes of a lattice row (nine population rows) and of one population row
   uint32_t bc, bm, bp;  // byte offsets of this thread's column and its neighbours
   bool out;             // this thread stores a cell of the second step
   float G, tau, omega;
@@ -843,23 +847,17 @@ struct Fused2 {
     asm volatile("" : "+v"(v));
     return v;
   }
-  template <class P>
-  __device__ __forceinline__ static P at(P base, uint32_t boff) {
-    using C = typename std::conditional<std::is_const<typename std::remove_pointer<P>::type>::value,
-                                        const char, char>::type;
-    return reinterpret_cast<P>(reinterpret_cast<__attribute__((address_space(1))) C*>(base) + boff);
+  // Buffer resource over `bytes` bytes from base + y * pitch (one population
+  // row of lattice row y when base is the population's row 0).
+  __device__ __forceinline__ static __amdgpu_buffer_rsrc_t rows(uint64_t base, int y,
+                                                               uint32_t pitch, uint32_t bytes) {
+    const uint64_t a = uniform(base + (uint64_t)(uint32_t)y * pitch);
+    return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(a), (short)0, (int)bytes,
+                                             0x00020000);
   }
-  __device__ __forceinline__ gptr<const T> in_row(int i, int y) const {
-    return as_global<const T>(uniform(src + row_index(i, y, nx, ny) * sizeof(T)));
-  }
-  __device__ __forceinline__ gptr<T> out_row(int i, int y) const {
-    return as_global<T>(uniform(dst + row_index(i, y, nx, ny) * sizeof(T)));
-  }
-  __device__ __forceinline__ gptr<const T> rhat_in(int y) const {
-    return as_global<const T>(uniform(src + rhat_row(y, nx, ny) * sizeof(T)));
-  }
-  __device__ __forceinline__ gptr<T> rhat_out(int y) const {
-    return as_global<T>(uniform(dst + rhat_row(y, nx, ny) * sizeof(T)));
+  // Load at byte `off` of the row that starts at the (wave-uniform) address row.
+  __device__ __forceinline__ static T ld(uint64_t row, uint32_t off) {
+    return *reinterpret_cast<gptr<const T>>(reinterpret_cast<gptr<const char>>(uniform(row)) + off);
   }
 
   __device__ __forceinline__ void setup(const InstDesc* __restrict__ dp, const TileItem& ti,
@@ -878,6 +876,10 @@ struct Fused2 {
     const uint64_t a = dp->pop[0], b = dp->pop[1];
     src = par ? b : a;
     dst = par ? a : b;
+    qsrc = src + rhat_row(0, nx, ny) * sizeof(T);
+    qdst = dst + rhat_row(0, nx, ny) * sizeof(T);
+    prow = (uint32_t)nx * (uint32_t)sizeof(T);
+    lrow = 9u * prow;
     const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
 #pragma unroll
     for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
@@ -890,10 +892,13 @@ struct Fused2 {
     out = t >= 3 && t - 3 < wcols;
   }
 
-  // Lattice row of march position j (any j in [-3, h + 2]).
+  // Lattice row of march position j (any j in [-3, h + 2]).  As y0 + h <= ny
+  // the unwrapped row lies in [-3, ny + 2]: one wrap maps it into the grid
+  // once ny >= 3, and for ny = 1 or 2 the row is its low bits.
   __device__ __forceinline__ int row_of(int j) const {
-    int y = (dir ? y0 + h - 1 - j : y0 + j) % ny;
-    return y < 0 ? y + ny : y;
+    const int y = dir ? y0 + h - 1 - j : y0 + j;
+    const int w = y < 0 ? y + ny : (y >= ny ? y - ny : y);
+    return ny < 3 ? (y & (ny - 1)) : w;
   }
 
   // Issues the loads of row j's pulled populations (f_i(x) = A_i(x - e_i))
@@ -903,25 +908,30 @@ struct Fused2 {
     const int y = row_of(j);
     const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
     const uint32_t c = fresh(bc), m = fresh(bm), p = fresh(bp);
-    v[0] = *at(in_row(0, y), c);
-    v[1] = *at(in_row(1, y), m);
-    v[2] = *at(in_row(2, ym), c);
-    v[3] = *at(in_row(3, y), p);
-    v[4] = *at(in_row(4, yp), c);
-    v[5] = *at(in_row(5, ym), m);
-    v[6] = *at(in_row(6, ym), p);
-    v[7] = *at(in_row(7, yp), p);
-    v[8] = *at(in_row(8, yp), m);
+    const uint64_t r0 = src + (uint64_t)(uint32_t)y * lrow, rm = src + (uint64_t)(uint32_t)ym * lrow,
+                   rp = src + (uint64_t)(uint32_t)yp * lrow;
+    v[0] = ld(r0, c);
+    v[1] = ld(r0 + prow, m);
+    v[2] = ld(rm + 2 * prow, c);
+    v[3] = ld(r0 + 3 * prow, p);
+    v[4] = ld(rp + 4 * prow, c);
+    v[5] = ld(rm + 5 * prow, m);
+    v[6] = ld(rm + 6 * prow, p);
+    v[7] = ld(rp + 7 * prow, p);
+    v[8] = ld(rp + 8 * prow, m);
     if constexpr (S::kCellShift) {
-      q[0] = *at(rhat_in(y), c);
-      q[1] = *at(rhat_in(y), m);
-      q[2] = *at(rhat_in(ym), c);
-      q[3] = *at(rhat_in(y), p);
-      q[4] = *at(rhat_in(yp), c);
-      q[5] = *at(rhat_in(ym), m);
-      q[6] = *at(rhat_in(ym), p);
-      q[7] = *at(rhat_in(yp), p);
-      q[8] = *at(rhat_in(yp), m);
+      const uint64_t q0 = qsrc + (uint64_t)(uint32_t)y * prow,
+                     qm = qsrc + (uint64_t)(uint32_t)ym * prow,
+                     qp = qsrc + (uint64_t)(uint32_t)yp * prow;
+      q[0] = ld(q0, c);
+      q[1] = ld(q0, m);
+      q[2] = ld(qm, c);
+      q[3] = ld(q0, p);
+      q[4] = ld(qp, c);
+      q[5] = ld(qm, m);
+      q[6] = ld(qm, p);
+      q[7] = ld(qp, p);
+      q[8] = ld(qp, m);
     }
   }
 
@@ -961,11 +971,10 @@ struct Fused2 {
   // hardware drops those stores.  No branch around the stores, so the wait
   // counts before the next loads stay exact (loads issued before a
   // branch-skipped store block would otherwise be waited for with the stores).
-  template <class V>
-  __device__ __forceinline__ void put(gptr<V> row, uint32_t off, V v) const {
-    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(
-        (void*)row, (short)0, nx * (int)sizeof(V), 0x00020000);
-    if constexpr (sizeof(V) == 4)
+  // (One resource for the nine rows with the population's row as a scalar
+  // offset takes fewer scalar instructions but ran 2% slower in FP32.)
+  __device__ __forceinline__ static void put(__amdgpu_buffer_rsrc_t r, uint32_t off, T v) {
+    if constexpr (sizeof(T) == 4)
       __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)off, 0,
                                             S::kStream ? 2 : 0);  // 2: non-temporal
     else
@@ -979,11 +988,11 @@ struct Fused2 {
       const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
       const T rh = S::ref(f[9]);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) put(out_row(i, y), c, S::encode(f[i], rh, ws[i]));
-      put(rhat_out(y), c, rh);
+      for (int i = 0; i < 9; ++i) put(rows(dst + i * prow, y, lrow, prow), c, S::encode(f[i], rh, ws[i]));
+      put(rows(qdst, y, prow, prow), c, rh);
     } else {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) put(out_row(i, y), c, S::pack(f[i], sh[i]));
+      for (int i = 0; i < 9; ++i) put(rows(dst + i * prow, y, lrow, prow), c, S::pack(f[i], sh[i]));
     }
   }
 };
