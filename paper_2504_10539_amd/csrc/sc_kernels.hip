@@ -40,8 +40,9 @@ __device__ __forceinline__ void diag_zero(double (&acc)[10]) {
 // Diagnostics of one cell (its pre-collision populations f; FP64 rho of the
 // rows below, at and above it in dn, md, up, column c): Eq. (16) with
 // periodic wrap, threshold of Eq. (9) strict.
-__device__ __forceinline__ void diag_cell(double (&acc)[10], const float (&f)[10], int c,
-                                          const double* dn, const double* md, const double* up) {
+__device__ __forceinline__ void diag_cell(double (&acc)[10], const float (&f)[10], int c, int cl,
+                                          int cr, const double* dn, const double* md,
+                                          const double* up) {
   bool fin = true;
 #pragma unroll
   for (int i = 0; i < 9; ++i) fin = fin && isfinite(f[i]);
@@ -50,7 +51,7 @@ __device__ __forceinline__ void diag_cell(double (&acc)[10], const float (&f)[10
                     ((double)f[8] - (double)f[7]);
   const double jy = ((double)f[2] - (double)f[4]) + ((double)f[5] - (double)f[8]) +
                     ((double)f[6] - (double)f[7]);
-  const double gx = (md[c + 1] - md[c - 1]) / 2.0;
+  const double gx = (md[cr] - md[cl]) / 2.0;
   const double gy = (up[c] - dn[c]) / 2.0;
   const double g = sqrt(gx * gx + gy * gy);
   acc[0] += r;
@@ -253,7 +254,7 @@ struct Strip {
   __device__ __forceinline__ void diag_zero() { sclbm::diag_zero(acc); }
   __device__ __forceinline__ void diag_cell(const float (&f)[10], int c, const double* dn,
                                             const double* md, const double* up) {
-    sclbm::diag_cell(acc, f, c, dn, md, up);
+    sclbm::diag_cell(acc, f, c, c - 1, c + 1, dn, md, up);
   }
 
   // Collide the row at march position r (psi of positions r-1, r, r+1 already
@@ -836,6 +837,7 @@ struct Fused2 {
   uint32_t lrow, prow;  // bytes of a lattice row (nine population rows) and of one population row
   uint32_t bc, bm, bp;  // byte offsets of this thread's column and its neighbours
   bool out;             // this thread stores a cell of the second step
+  bool wrap;            // the grid is one periodic strip (nx <= NT)
   float G, tau, omega;
 
   __device__ __forceinline__ static uint64_t uniform(uint64_t v) {
@@ -889,7 +891,11 @@ struct Fused2 {
     bc = (uint32_t)c * (uint32_t)sizeof(T);
     bm = (uint32_t)wrap_dec(c, nx) * (uint32_t)sizeof(T);
     bp = (uint32_t)wrap_inc(c, nx) * (uint32_t)sizeof(T);
-    out = t >= 3 && t - 3 < wcols;
+    // A grid no wider than the workgroup is marched as one periodic strip
+    // (x0 = 0): ring column x < nx holds lattice column (x - 3) mod nx, the
+    // ring's neighbours wrap at nx, and every column is written.
+    wrap = nx <= NT;
+    out = wrap ? t < nx : (t >= 3 && t - 3 < wcols);
   }
 
   // Lattice row of march position j (any j in [-3, h + 2]).  As y0 + h <= ny
@@ -997,12 +1003,12 @@ struct Fused2 {
   }
 };
 
-// Interaction force at thread t from three psi ring rows: dn holds row y - 1,
-// md row y, up row y + 1 (LDS index = thread).
+// Interaction force at ring column t from three psi ring rows: dn holds row
+// y - 1, md row y, up row y + 1; l and r are the ring columns left and right
+// of t.
 __device__ __forceinline__ void ring_force(const float* dn, const float* md, const float* up, int t,
-                                           float G, float& Fx, float& Fy) {
-  force_of(md[t], md[t + 1], up[t], md[t - 1], dn[t], up[t + 1], up[t - 1], dn[t - 1], dn[t + 1], G,
-           Fx, Fy);
+                                           int l, int r, float G, float& Fx, float& Fy) {
+  force_of(md[t], md[r], up[t], md[l], dn[t], up[r], up[l], dn[l], dn[r], G, Fx, Fy);
 }
 
 // Ring slot of march row r >= -9 (three rows of each ring are live at a time).
@@ -1049,11 +1055,12 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
   __shared__ double rr[DIAG ? 3 : 1][DIAG ? NT : 1];  // FP64 rho(t) rows
   const int nitems = *nitems_p;
   const int t = strip_slot<S, NT>();  // LDS ring index
-  const bool stage_a = t >= 1 && t <= NT - 2;
-  const bool stage_b = t >= 2 && t <= NT - 3;
-  // Lanes that store nothing still run the last collision (on clamped ring
-  // columns) so that the row's stores need no branch.
-  const int tf = min(max(t, 1), NT - 2);
+  // Columns each stage is valid for: a strip loses one halo column per side
+  // to every stencil.  Lanes that store nothing still run the last collision
+  // (on clamped ring columns) so that the row's stores need no branch.
+  const bool strip_a = t >= 1 && t <= NT - 2;
+  const bool strip_b = t >= 2 && t <= NT - 3;
+  const int strip_f = min(max(t, 1), NT - 2);
   const int op[10] = {0, 0, 0, 0, 0, 1, 0, 0, 1, 2};  // sum, max, min
   (void)op;
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -1069,8 +1076,20 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
       // that every ring access is the lane's LDS address plus a constant.  In
       // march order the row below a row (y - 1) is the previous one when
       // marching downwards and the next one when marching upwards.
-      auto march = [&](auto upward) {
+      auto march = [&](auto upward, auto wrap_c) {
       const int below = upward ? 1 : -1;
+      // A periodic strip loses no column to the stencils: its lanes t >= nx
+      // only decode, and tl and tr, the ring neighbours of column t, wrap at
+      // nx.  (Instantiated apart from the plain strip, whose code it would
+      // otherwise change.)
+      constexpr bool kW = decltype(wrap_c)::value;
+      const int nx = s.nx;
+      const bool stage_a = kW ? t < nx : strip_a;
+      const bool stage_b = kW ? t < nx : strip_b;
+      const int tl = kW ? (t == 0 ? nx - 1 : t - 1) : t - 1;
+      const int tr = kW ? (t == nx - 1 ? 0 : min(t + 1, NT - 1)) : t + 1;
+      const int tf = kW ? t : strip_f;
+      const int tfl = kW ? tl : tf - 1, tfr = kW ? tr : tf + 1;
       RawCell<S> raw[kInPlace ? 1 : NR];
       float fa[NF][10], fb[2][10];
       // Row R (>= -3) of the first step is loaded into slot R mod NR.
@@ -1109,11 +1128,12 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         __syncthreads();
         if constexpr (DIAG) {  // the state read, row j + 2, before its collision
           if ((unsigned)(j + 2) < (unsigned)h && s.out)
-            diag_cell(acc, fa_p, t, rr[ring(2 + below)], rr[ring(2)], rr[ring(2 - below)]);
+            diag_cell(acc, fa_p, t, tl, tr, rr[ring(2 + below)], rr[ring(2)], rr[ring(2 - below)]);
         }
         if ((!kLead || j >= -4) && stage_a) {  // row j + 2
           float Fx, Fy;
-          ring_force(psa[ring(2 + below)], psa[ring(2)], psa[ring(2 - below)], t, s.G, Fx, Fy);
+          ring_force(psa[ring(2 + below)], psa[ring(2)], psa[ring(2 - below)], t, tl, tr, s.G, Fx,
+                     Fy);
           const float rho = fa_p[9];
           collide<S::kRecip>(fa_p, rho, Fx, Fy, s.tau, s.omega);
 #pragma unroll
@@ -1126,21 +1146,21 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
           const float(*md)[NT] = fs[ring(1)];
           const float(*up)[NT] = fs[ring(1 - below)];
           fb_c[0] = md[0][t];
-          fb_c[1] = md[1][t - 1];
+          fb_c[1] = md[1][tl];
           fb_c[2] = dn[2][t];
-          fb_c[3] = md[3][t + 1];
+          fb_c[3] = md[3][tr];
           fb_c[4] = up[4][t];
-          fb_c[5] = dn[5][t - 1];
-          fb_c[6] = dn[6][t + 1];
-          fb_c[7] = up[7][t + 1];
-          fb_c[8] = up[8][t - 1];
+          fb_c[5] = dn[5][tl];
+          fb_c[6] = dn[6][tr];
+          fb_c[7] = up[7][tr];
+          fb_c[8] = up[8][tl];
           fb_c[9] = density(fb_c);
           psb[ring(1)][t] = psi_of(fb_c[9]);
         }
         __syncthreads();
         if constexpr (!kLead) {
           float Fx, Fy;
-          ring_force(psb[ring(below)], psb[ring(0)], psb[ring(-below)], tf, s.G, Fx, Fy);
+          ring_force(psb[ring(below)], psb[ring(0)], psb[ring(-below)], tf, tfl, tfr, s.G, Fx, Fy);
           collide<S::kRecip>(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
           s.store(j, fb_p);
         }
@@ -1158,12 +1178,18 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         if (j0 + decltype(u)::value < h) pos(std::false_type{}, u, j0 + decltype(u)::value);
       });
       };
-      if constexpr (!kFixedRing)
-        march(s.dir != 0);
-      else if (s.dir)
-        march(std::true_type{});
+      auto go = [&](auto wrap_c) {
+        if constexpr (!kFixedRing)
+          march(s.dir != 0, wrap_c);
+        else if (s.dir)
+          march(std::true_type{}, wrap_c);
+        else
+          march(std::false_type{}, wrap_c);
+      };
+      if (s.wrap)
+        go(std::true_type{});
       else
-        march(std::false_type{});
+        go(std::false_type{});
     }
     if constexpr (DIAG) {
       block_reduce<10>(acc, op);

@@ -100,7 +100,7 @@ WorkLayout work_layout(int nx, int ny) {
 // a band boundary reach the rows they share at the same time (both at the
 // start or both at the end of their march) and read them once from L2.
 void make_items(int nx, int ny, int storage, int tile, int inst, std::vector<TileItem>& out) {
-  const int sw = tile_width(tile), rows = band_rows(tile, nx, ny, storage);
+  const int sw = strip_width(tile, nx), rows = band_rows(tile, nx, ny, storage);
   int band = 0;
   for (int y0 = 0; y0 < ny; y0 += rows, ++band)
     for (int x0 = 0; x0 < nx; x0 += sw)
@@ -140,7 +140,8 @@ static int resident_blocks(int storage, int variant) {
 int band_rows(int k, int nx, int ny, int storage) {
   const int r = tile_rows(k);
   if (r > 0) return r;
-  const int strips = (nx + tile_width(k) - 1) / tile_width(k);
+  const int sw = strip_width(k, nx);
+  const int strips = (nx + sw - 1) / sw;
   const int bands = std::max(1, kBalancedRounds * resident_blocks(storage, tile_variant(k)) / strips);
   return std::min(std::max((ny + bands - 1) / bands, kMinRows), kMaxBalancedRows);
 }
@@ -733,7 +734,8 @@ int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int ti
     if (c->p.storage != storage) continue;
     int k = member_tile(c, variant, tile_override);  // as make_items tiles it
     if (tail) k = tail_variant_for(variant) * kNumRows + k % kNumRows;
-    const int sw = tile_width(k), rows = band_rows(k, c->p.nx, c->p.ny, storage);
+    const int sw = strip_width(k, c->p.nx);
+    const int rows = band_rows(k, c->p.nx, c->p.ny, storage);
     n += ((c->p.nx + sw - 1) / sw) * ((c->p.ny + rows - 1) / rows);
   }
   return n;
@@ -1025,7 +1027,7 @@ lbm_status lbm_tile_layout(const lbm_params* p, int32_t k, int32_t* rows, int32_
   if (v != LBM_OK) return v;
   if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
   const int r = band_rows(k, p->nx, p->ny, p->storage);
-  const int w = tile_width(k);
+  const int w = strip_width(k, p->nx);
   if (rows) *rows = r;
   if (items) *items = ((p->nx + w - 1) / w) * ((p->ny + r - 1) / r);
   return LBM_OK;

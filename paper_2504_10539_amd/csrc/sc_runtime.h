@@ -34,6 +34,13 @@ inline int tile_width(int k) {
   if (v.steps == 2) return v.width;
   return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
 }
+// Columns one work item of tile shape k covers on a grid nx columns wide: a
+// two-step shape marches a grid no wider than its workgroup as one periodic
+// strip.
+inline int strip_width(int k, int nx) {
+  const StepVariant& v = step_variant(tile_variant(k));
+  return v.steps == 2 && nx <= v.threads ? nx : tile_width(k);
+}
 // Time steps one launch of tile shape k takes.
 inline int tile_steps(int k) { return step_variant(tile_variant(k)).steps; }
 // Index of the step variant with these parameters (-1 if there is none).

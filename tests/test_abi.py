@@ -134,6 +134,14 @@ def test_tile_layout(lbm):
         else:
             assert 2 <= rows <= 256
         assert items == -(-300 // t["width"]) * -(-77 // rows)
+    # a grid no wider than a two-step workgroup is one periodic strip
+    for t in tiles:
+        if t["rows"] != 8:
+            continue
+        for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL):
+            rows, items = lbm.tile_layout(256, 64, t["id"], st)
+            one = t["steps"] == 2 and t["threads"] >= 256
+            assert items == (1 if one else -(-256 // t["width"])) * 8, (t, st)
     bal = next(t for t in tiles if t["rows"] == 0 and t["steps"] == 2 and t["threads"] == 256)
     rows, items = lbm.tile_layout(4096, 4096, bal["id"], lbm.LBM_F16_SHIFTED)
     assert 2 <= rows <= 256 and items == 17 * -(-4096 // rows)

@@ -38,12 +38,14 @@ def _rho0(storage):
 
 
 @pytest.mark.parametrize("storage", [0, 1, 2])
-@pytest.mark.parametrize("nx,ny", [(1, 1), (5, 3), (40, 9), (250, 2), (251, 13), (300, 77),
-                                   (513, 5)])
+@pytest.mark.parametrize("nx,ny", [(1, 1), (2, 5), (5, 3), (40, 9), (127, 6), (128, 4),
+                                   (250, 2), (251, 13), (254, 3), (255, 6), (256, 7), (300, 77),
+                                   (512, 3), (513, 5)])
 def test_two_step_shapes_match_single_step(storage, nx, ny):
     """Strips narrower than the halo, one-row and short last bands, widths
-    around the strip width; 7 steps as 1 + 6 (one single-step launch, then
-    three two-step launches)."""
+    around the strip width and the workgroup width (grids up to the
+    workgroup's width run as one periodic strip); 7 steps as 1 + 6 (one
+    single-step launch, then three two-step launches)."""
     L = lbm()
     f0 = f32_state(inputs.random_positive_state(nx, ny, seed=nx * 7 + ny))
     ref = L.Simulation(nx, ny, -5.5, 0.8, storage, _rho0(storage))
