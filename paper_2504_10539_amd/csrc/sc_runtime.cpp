@@ -180,6 +180,15 @@ int default_tile(const lbm_params& p) {
   // 256 threads, 2 rows in flight, balanced bands; else 128 threads, 16-row
   // bands from 4M cells, 4-row from 1M); FP16 shifted per cell from 16M cells
   // (as FP16-shifted).
+  // Below a million cells, a grid no wider than a two-step workgroup runs as
+  // one periodic strip, two steps per launch, balanced bands: 128 threads up
+  // to 128 columns, 256 up to 256, else 512; FP16 per cell with 2 rows in
+  // flight and at least 256 threads.
+  if (cells < (1u << 20) && p.nx <= 512) {
+    const bool percell = p.storage == LBM_F16_CELL;
+    const int nt = p.nx <= 128 && !percell ? 128 : (p.nx <= 256 ? 256 : 512);
+    return find_variant(nt, 1, percell ? 2 : 1, 0, 2) * kNumRows + row_choice(0);
+  }
   if (p.storage == LBM_F32 && cells >= (4u << 20))
     return find_variant(256, 1, 1, 0, 2, 240) * kNumRows + row_choice(8);
   if (p.storage == LBM_F32 && cells >= (1u << 20))
