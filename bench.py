@@ -345,7 +345,9 @@ def run_serving(args, torch, lbm, inputs):
         for r in trace:
             while srv.clock() - t0 < r.arrival:
                 time.sleep(min(0.001, max(0.0, r.arrival - (srv.clock() - t0))))
-            tickets.append(srv.submit(r.n, r.n, r.G, r.tau, r.steps, r.drops, seed=r.seed))
+            tickets.append(srv.submit(r.n, r.n, r.G, r.tau, r.steps, r.drops, seed=r.seed,
+                                      storage=args.serve_storage,
+                                      rho0=1.0 if args.serve_storage == lbm.LBM_F16_SHIFTED else 0.0))
             if len(tickets) % 250 == 0:
                 log(f"[serving {name}] {len(tickets)} submitted, {srv.stats()['completed']} done")
         last = time.perf_counter()
@@ -365,7 +367,8 @@ def run_serving(args, torch, lbm, inputs):
         srv.close()
         lat.sort()
         makespan = max(done) - t0
-        res[name] = {"requests": len(trace), "aggregate_mlups": st["lattice_updates"] / makespan / 1e6,
+        res[name] = {"requests": len(trace), "storage": ["f32", "f16_shifted", "f16_cell"][args.serve_storage],
+                     "aggregate_mlups": st["lattice_updates"] / makespan / 1e6,
                      "p50_ms": 1e3 * lat[len(lat) // 2],
                      "p99_ms": 1e3 * lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
                      "makespan_s": makespan, "unstable": unstable,
@@ -422,6 +425,8 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=2048)
     ap.add_argument("--serve-smax", type=int, default=20000)
     ap.add_argument("--serve-pool-gb", type=int, default=32)
+    ap.add_argument("--serve-storage", type=int, default=0, choices=[0, 1, 2],
+                    help="storage form of every request (0 FP32, 1 FP16-shifted, 2 FP16 per cell)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

@@ -474,18 +474,20 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
   // Engine workspace lives at the top of the pool.
   size_t eng_bytes = 0;
   if (!opts->fake_executor && opts->policy == LBM_POLICY_CONTINUOUS) {
-    // Strip variants, valid for every request width: 256-thread strips suit
-    // the range of request sizes (64 .. 2048 columns) better than wider ones.
-    // FP32 takes two steps per launch on 64-byte-aligned 240-column strips (a
-    // tail launch takes the odd last step of a tick); FP16 storage one.
+    // Two-step strip variants, valid for every request width: 256-thread
+    // strips suit the range of request sizes (64 .. 2048 columns) better than
+    // wider ones.  FP32 on 64-byte-aligned 240-column strips, the FP16 forms
+    // on 250-column strips (per-cell shift with 2 rows in flight); a request
+    // up to 256 columns wide is one periodic strip, and a tail launch takes
+    // the odd last step of a tick.
     const int v = find_variant(256, 1, 1, 0, 2, 240);
     const int sw = tile_width(v * kNumRows);
     const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
                                           1u << 22);
     const int cap_items[kNumStorages] = {per, per, per};
-    const int cap_titems[kNumStorages] = {per, 0, 0};
-    const int v16 = find_variant(256, 2, 1, 0);
-    const int variants[kNumStorages] = {v, v16, v16};
+    const int cap_titems[kNumStorages] = {per, per, per};
+    const int variants[kNumStorages] = {v, find_variant(256, 1, 1, 0, 2, 250),
+                                        find_variant(256, 1, 2, 0, 2, 250)};
     eng_bytes = align_up(
         BatchEngine::work_bytes(opts->max_slots, cap_items, cap_titems, opts->steps_per_tick), 256);
     if (eng_bytes >= pool_bytes / 2) {
