@@ -174,35 +174,35 @@ int default_strip_tile(const lbm_params& p) {
 
 int default_tile(const lbm_params& p) {
   const size_t cells = (size_t)p.nx * (size_t)p.ny;
-  // From a million cells up, two steps per launch wherever that measured
-  // faster: FP32 (from 4M cells 256 threads writing 240 columns, 8-row
-  // bands; else 128 threads with 4-row bands); FP16-shifted (from 16M cells
-  // 256 threads, 2 rows in flight, balanced bands; else 128 threads, 16-row
-  // bands from 4M cells, 4-row from 1M); FP16 shifted per cell from 16M cells
-  // (as FP16-shifted).
+  // From a million cells up, two steps per launch: FP32 with 256 threads
+  // writing 240 columns (64-byte-aligned strips), 8-row bands; FP16-shifted
+  // from 16M cells with 256 threads, 2 rows in flight and balanced bands,
+  // below that with 128 threads (8-row bands below 4M cells, else balanced);
+  // FP16 shifted per cell with 256 threads and 2 rows in flight (balanced
+  // bands from 16M cells, 16-row from 4M, 8-row below).
+  if (cells >= (1u << 20)) {
+    if (p.storage == LBM_F32) return find_variant(256, 1, 1, 0, 2, 240) * kNumRows + row_choice(8);
+    if (p.storage == LBM_F16_SHIFTED && cells >= (16u << 20))
+      return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
+    if (p.storage == LBM_F16_SHIFTED)
+      return find_variant(128, 1, 1, 0, 2) * kNumRows + row_choice(cells >= (4u << 20) ? 0 : 8);
+    return find_variant(256, 1, 2, 0, 2) * kNumRows +
+           row_choice(cells >= (16u << 20) ? 0 : (cells >= (4u << 20) ? 16 : 8));
+  }
   // Below a million cells, a grid no wider than a two-step workgroup runs as
   // one periodic strip, two steps per launch, balanced bands: 128 threads up
   // to 128 columns, 256 up to 256, else 512; FP16 per cell with 2 rows in
   // flight and at least 256 threads.
-  if (cells < (1u << 20) && p.nx <= 512) {
+  if (p.nx <= 512) {
     const bool percell = p.storage == LBM_F16_CELL;
     const int nt = p.nx <= 128 && !percell ? 128 : (p.nx <= 256 ? 256 : 512);
     return find_variant(nt, 1, percell ? 2 : 1, 0, 2) * kNumRows + row_choice(0);
   }
-  if (p.storage == LBM_F32 && cells >= (4u << 20))
-    return find_variant(256, 1, 1, 0, 2, 240) * kNumRows + row_choice(8);
-  if (p.storage == LBM_F32 && cells >= (1u << 20))
-    return find_variant(128, 1, 1, 0, 2) * kNumRows + row_choice(4);
-  if (p.storage == LBM_F16_SHIFTED && cells >= (16u << 20))
-    return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
-  if (p.storage == LBM_F16_SHIFTED && cells >= (1u << 20))
-    return find_variant(128, 1, 1, 0, 2) * kNumRows + row_choice(cells >= (4u << 20) ? 16 : 4);
-  if (p.storage == LBM_F16_CELL && cells >= (16u << 20))
-    return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
-  // FP16 storage: paired columns, 4 wavefronts, 2 rows in flight, 4-row
-  // bands (2 below a million cells), where the grid allows it.
+  // FP16 storage below a million cells on grids wider than 512 columns:
+  // paired columns, 4 wavefronts, 2 rows in flight, 2-row bands, where the
+  // grid allows it.
   if (p.storage != LBM_F32) {
-    const int k = find_variant(256, 2, 2, 1) * kNumRows + row_choice(cells >= (1u << 20) ? 4 : 2);
+    const int k = find_variant(256, 2, 2, 1) * kNumRows + row_choice(2);
     if (tile_valid(k, p.nx)) return k;
   }
   return default_strip_tile(p);
