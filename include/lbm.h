@@ -207,9 +207,11 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * populations kept on chip (rounded to the storage type as a store would
  * round them); such a strip reads three halo columns on each side of its
  * `width`, which is threads - 6 or a multiple of 16 below that (strips that
- * start and end on 64-byte boundaries in FP32).  rows = 0: balanced bands, whose height is chosen per grid so
- * that a launch is about two rounds of the workgroups the device holds at
- * once (lbm_tile_layout gives it).  Every shape computes bitwise the same
+ * start and end on 64-byte boundaries in FP32), and a grid no wider than
+ * `threads` is marched as one periodic strip with no halo columns.  rows = 0:
+ * balanced bands, whose height is chosen per grid so that a launch is about
+ * two rounds of the workgroups the device holds at once (lbm_tile_layout
+ * gives it).  Every shape computes bitwise the same
  * result; only speed differs.  Any output pointer may be NULL; k out of range
  * is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
