@@ -222,6 +222,10 @@ lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* 
  * the step kernel's occupancy on the current device.  Either output may be
  * NULL; invalid parameters or k out of range are LBM_EINVAL. */
 lbm_status lbm_tile_layout(const lbm_params* p, int32_t k, int32_t* rows, int32_t* items);
+/* The built-in tile shape a run with these parameters starts with when the
+ * tuning cache has no entry for it (*k; measured defaults by storage type and
+ * grid size).  Invalid parameters are LBM_EINVAL. */
+lbm_status lbm_default_tile(const lbm_params* p, int32_t* k);
 lbm_status lbm_set_tile(lbm_ctx* ctx, int32_t k);
 int32_t lbm_get_tile(const lbm_ctx* ctx);
 

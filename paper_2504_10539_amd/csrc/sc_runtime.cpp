@@ -1031,6 +1031,14 @@ lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* 
   return LBM_OK;
 }
 
+lbm_status lbm_default_tile(const lbm_params* p, int32_t* k) {
+  const lbm_status v = validate_params(p);
+  if (v != LBM_OK) return v;
+  if (!k) return fail(LBM_EINVAL, "k is NULL");
+  *k = default_tile(*p);
+  return LBM_OK;
+}
+
 lbm_status lbm_tile_layout(const lbm_params* p, int32_t k, int32_t* rows, int32_t* items) {
   const lbm_status v = validate_params(p);
   if (v != LBM_OK) return v;

@@ -120,6 +120,7 @@ _PROTOS = {
     "lbm_tile_describe": (_i32, [_i32, _P(_i32), _P(_i32), _P(_i32), _P(_i32), _P(_i32),
                                  _P(_i32), _P(_i32)]),
     "lbm_tile_layout": (_i32, [_P(lbm_params), _i32, _P(_i32), _P(_i32)]),
+    "lbm_default_tile": (_i32, [_P(lbm_params), _P(_i32)]),
     "lbm_set_tile": (_i32, [_vp, _i32]),
     "lbm_get_tile": (_i32, [_vp]),
     "lbm_autotune": (_i32, [_vp, _i32, _P(_i32)]),
@@ -256,6 +257,14 @@ def tile_layout(nx: int, ny: int, k: int, storage: int = LBM_F32) -> tuple[int, 
     _check(LIB.lbm_tile_layout(ctypes.byref(p), int(k), ctypes.byref(rows), ctypes.byref(items)),
            "lbm_tile_layout")
     return rows.value, items.value
+
+
+def default_tile(nx: int, ny: int, storage: int = LBM_F32) -> int:
+    """The built-in tile shape an nx x ny run starts with (no tuning-cache entry)."""
+    p = make_params(nx, ny, -5.0, 1.0, storage, 1.0 if storage == LBM_F16_SHIFTED else 0.0)
+    k = _i32()
+    _check(LIB.lbm_default_tile(ctypes.byref(p), ctypes.byref(k)), "lbm_default_tile")
+    return k.value
 
 
 class Simulation:

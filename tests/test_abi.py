@@ -149,3 +149,25 @@ def test_tile_layout(lbm):
     assert lbm.LIB.lbm_tile_layout(None, 0, ctypes.byref(r), None) == lbm.LBM_EINVAL
     p = lbm.make_params(64, 64, -5.0, 1.0)
     assert lbm.LIB.lbm_tile_layout(ctypes.byref(p), len(tiles), None, None) == lbm.LBM_EINVAL
+
+
+def test_default_tile(lbm):
+    """Built-in shapes: a valid shape for every grid; two steps per launch from
+    a million cells; below that a grid up to 512 columns wide is one periodic
+    two-step strip with balanced bands."""
+    tiles = lbm.tiles()
+    for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL):
+        for nx, ny in ((1, 1), (64, 64), (97, 300), (128, 128), (256, 256), (300, 77), (512, 512),
+                       (513, 100), (1000, 1000), (1024, 1024), (2047, 2048), (4096, 4096)):
+            t = tiles[lbm.default_tile(nx, ny, st)]
+            if t["paired"]:
+                assert nx % 2 == 0 and nx >= 128, (nx, ny, st, t)
+            if nx * ny >= 1 << 20:
+                assert t["steps"] == 2, (nx, ny, st, t)
+            elif nx <= 512:
+                assert t["steps"] == 2 and t["threads"] >= nx and t["rows"] == 0, (nx, ny, st, t)
+    k = ctypes.c_int32()
+    p = lbm.make_params(0, 64, -5.0, 1.0)
+    assert lbm.LIB.lbm_default_tile(ctypes.byref(p), ctypes.byref(k)) == lbm.LBM_EINVAL
+    p = lbm.make_params(64, 64, -5.0, 1.0)
+    assert lbm.LIB.lbm_default_tile(ctypes.byref(p), None) == lbm.LBM_EINVAL
