@@ -337,7 +337,10 @@ def run_serving(args, torch, lbm, inputs):
     trace = inputs.serving_trace(args.serve_requests, rate=args.serve_rate, seed=4,
                                  nmax=args.serve_nmax, smax=args.serve_smax)
     res = {}
-    for policy, name in ((lbm.LBM_POLICY_CONTINUOUS, "continuous"), (lbm.LBM_POLICY_FIFO, "fifo")):
+    policies = ((lbm.LBM_POLICY_CONTINUOUS, "continuous"), (lbm.LBM_POLICY_FIFO, "fifo"))
+    for policy, name in policies:
+        if args.serve_policy not in ("both", name):
+            continue
         srv = lbm.Server(args.serve_pool_gb << 30, policy=policy, steps_per_tick=args.graph_steps,
                          max_slots=256)
         t0 = srv.clock()
@@ -425,6 +428,7 @@ def main():
     ap.add_argument("--serve-nmax", type=int, default=2048)
     ap.add_argument("--serve-smax", type=int, default=20000)
     ap.add_argument("--serve-pool-gb", type=int, default=32)
+    ap.add_argument("--serve-policy", choices=["both", "continuous", "fifo"], default="both")
     ap.add_argument("--serve-storage", type=int, default=0, choices=[0, 1, 2],
                     help="storage form of every request (0 FP32, 1 FP16-shifted, 2 FP16 per cell)")
     args = ap.parse_args()
