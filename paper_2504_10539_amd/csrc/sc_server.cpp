@@ -496,8 +496,10 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
     }
     s->eng.persistent = true;
     // One band height for every request: the persistent grid hands items out
-    // round-robin, which balances only items of similar size.
-    s->eng.row_override = row_choice(8);
+    // round-robin, which balances only items of similar size.  16 rows: on a
+    // saturated FP32 trace 4, 8, 16 and 32 rows served 92k, 101k, 104k and
+    // 104k MLUPS.
+    s->eng.row_override = row_choice(16);
     lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, cap_items,
                                cap_titems, variants, s->pool + pool_bytes - eng_bytes, eng_bytes);
     if (r != LBM_OK) {
