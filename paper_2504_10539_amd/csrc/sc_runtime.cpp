@@ -595,6 +595,7 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
       hipGraphNode_t node;
       SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, variant[s], d_desc, d_items[s],
                                d_nitems[s], grid[s], j));
+      step_nodes[s].push_back(node);
       prev = node;
     }
   for (int s = 0; s < kNumStorages; ++s) {
@@ -602,11 +603,17 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
     hipGraphNode_t node;
     SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, tail_variant[s], d_desc, d_titems[s],
                              d_tnitems[s], tgrid[s], kTailSub));
+    step_nodes[s].push_back(node);
     prev = node;
   }
   hipGraphNode_t last;
   SCLBM_HIP(graph_add_tick(graph, &last, &prev, 1, false, d_desc, cap_inst, K));
   SCLBM_HIP(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  for (int s = 0; s < kNumStorages; ++s) {
+    enabled[s] = !lazy_storages;
+    if (lazy_storages)
+      for (hipGraphNode_t n : step_nodes[s]) SCLBM_HIP(hipGraphNodeSetEnabled(exec, n, 0));
+  }
   return LBM_OK;
 }
 
@@ -650,6 +657,14 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
       }
     }
     hd[i] = d;
+  }
+  // A storage type's launches are enabled with its first members, with no
+  // replay in flight (so none already queued sees the change).
+  for (int s = 0; s < kNumStorages; ++s) {
+    if (enabled[s] || count[s] == 0) continue;
+    SCLBM_HIP(hipStreamSynchronize(stream));
+    for (hipGraphNode_t n : step_nodes[s]) SCLBM_HIP(hipGraphNodeSetEnabled(exec, n, 1));
+    enabled[s] = true;
   }
   SCLBM_HIP(hipMemcpyAsync(d_desc, hd, (size_t)cap_inst * sizeof(InstDesc),
                            hipMemcpyHostToDevice, stream));
@@ -707,6 +722,10 @@ void BatchEngine::destroy() {
     }
   exec = nullptr;
   graph = nullptr;
+  for (int s = 0; s < kNumStorages; ++s) {
+    step_nodes[s].clear();
+    enabled[s] = false;
+  }
 }
 
 // Tile a member uses inside a batch: the batch's override if set, else the

@@ -128,6 +128,12 @@ struct BatchEngine {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<lbm_ctx*> members;
+  // Storage types whose step launches start disabled in the graph and are
+  // enabled by the first load that has members of that type (a server that
+  // sees only one storage type then launches no empty kernels).
+  bool lazy_storages = false;
+  bool enabled[kNumStorages] = {};
+  std::vector<hipGraphNode_t> step_nodes[kNumStorages];
 
   // cap_titems: tail tile-table capacities (0 for single-step storage types).
   static size_t work_bytes(int cap_inst, const int cap_items[kNumStorages],

@@ -495,6 +495,7 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
       return fail(LBM_ENOMEM, "pool too small for the batch tables");
     }
     s->eng.persistent = true;
+    s->eng.lazy_storages = true;  // no empty launches for storage types not yet served
     // One band height for every request: the persistent grid hands items out
     // round-robin, which balances only items of similar size.  16 rows: on a
     // saturated FP32 trace 4, 8, 16 and 32 rows served 92k, 101k, 104k and
