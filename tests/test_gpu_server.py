@@ -7,6 +7,8 @@ different kernel variant) in every finite value and in which cells are not
 finite.  A
 request with unstable parameters is flagged without disturbing the others.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -123,4 +125,33 @@ def test_poisson_trace_completes_within_budget():
     assert st["completed"] == len(trace)
     assert st["pool_high_water"] <= pool
     assert all(c in (L.LBM_OK, L.LBM_EUNSTABLE) for c in codes)
+    srv.close()
+
+
+def test_storage_type_joining_a_running_server():
+    """FP16 requests that arrive while FP32 ticks are in flight: the server
+    enables that storage type's graph launches then; every result equals the
+    request served alone."""
+    L = lbm()
+    long_f32 = (512, -5.0, 1.0, 3000, [(256, 256, 60)], 0)
+    reqs = {100: long_f32}
+    reqs.update({k: r for k, r in enumerate(REQS) if r[5] != 0})
+    srv = L.Server(1 << 30, steps_per_tick=16, max_slots=8)
+    out = {100: _submit(srv, 100, long_f32)}
+    t0 = time.perf_counter()
+    while srv.stats()["ticks"] < 2:  # the FP32 run is under way
+        assert time.perf_counter() - t0 < 60
+        time.sleep(0.002)
+    for k, r in reqs.items():
+        if k != 100:
+            out[k] = _submit(srv, k, r)
+    srv.drain()
+    for k, (t, f) in out.items():
+        code = srv.poll(t)[0]
+        alone = L.Server(1 << 30, steps_per_tick=16, max_slots=8)
+        ta, fa = _submit(alone, k, reqs[k])
+        alone.drain()
+        assert alone.poll(ta)[0] == code
+        assert np.array_equal(_bits(f.cpu().numpy()), _bits(fa.cpu().numpy())), k
+        alone.close()
     srv.close()
