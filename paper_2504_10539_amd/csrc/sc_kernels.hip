@@ -287,7 +287,7 @@ struct Strip {
       float Fx, Fy;
       force_of(md[c], md[c + 1], up[c], md[c - 1], dn[c], up[c + 1], up[c - 1], dn[c - 1],
                dn[c + 1], G, Fx, Fy);
-      collide<S::kRecip>(f[k], f[k][9], Fx, Fy, tau, omega);
+      collide(f[k], f[k][9], Fx, Fy, tau, omega);
       const uint32_t xb = fresh((uint32_t)xc[k] * (uint32_t)sizeof(T));
       if constexpr (S::kCellShift) {
         const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
@@ -706,9 +706,9 @@ struct PairStrip {
     const PsiRow& up = dir ? prev : next;
     float Fx, Fy;
     force_of(md.a, md.b, up.a, md.l, dn.a, up.b, up.l, dn.l, dn.b, G, Fx, Fy);
-    collide<S::kRecip>(fa, md.rho_a, Fx, Fy, tau, omega);
+    collide(fa, md.rho_a, Fx, Fy, tau, omega);
     force_of(md.b, md.r, up.b, md.a, dn.b, up.r, up.a, dn.a, dn.r, G, Fx, Fy);
-    collide<S::kRecip>(fb, md.rho_b, Fx, Fy, tau, omega);
+    collide(fb, md.rho_b, Fx, Fy, tau, omega);
     if (out_ok) {
       const int y = row_of(r);
       const uint32_t o = lane_offset();
@@ -1135,7 +1135,7 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
           ring_force(psa[ring(2 + below)], psa[ring(2)], psa[ring(2 - below)], t, tl, tr, s.G, Fx,
                      Fy);
           const float rho = fa_p[9];
-          collide<S::kRecip>(fa_p, rho, Fx, Fy, s.tau, s.omega);
+          collide(fa_p, rho, Fx, Fy, s.tau, s.omega);
 #pragma unroll
           for (int i = 0; i < 9; ++i) fs[ring(2)][i][t] = s.through_storage(fa_p[i], i, rho);
         }
@@ -1161,7 +1161,7 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         if constexpr (!kLead) {
           float Fx, Fy;
           ring_force(psb[ring(below)], psb[ring(0)], psb[ring(-below)], tf, tfl, tfr, s.G, Fx, Fy);
-          collide<S::kRecip>(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
+          collide(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
           s.store(j, fb_p);
         }
       };
