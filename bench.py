@@ -332,11 +332,43 @@ def run_sweep(args, torch, lbm, inputs):
     return res
 
 
+def serving_capacity(args, torch, lbm, inputs):
+    """Closed-loop capacity of the continuous path, in requests per second: a
+    calibration batch of the trace's distribution (seed 40) submitted at once,
+    counted until 80% of it has completed (before the tail of the last long
+    requests leaves the GPU part-idle)."""
+    cal = inputs.serving_trace(args.serve_calib, rate=0.0, seed=40, nmax=args.serve_nmax,
+                               smax=args.serve_smax)
+    srv = lbm.Server(args.serve_pool_gb << 30, policy=lbm.LBM_POLICY_CONTINUOUS,
+                     steps_per_tick=args.graph_steps, max_slots=256)
+    t0 = srv.clock()
+    for r in cal:
+        srv.submit(r.n, r.n, r.G, r.tau, r.steps, r.drops, seed=r.seed, storage=args.serve_storage,
+                   rho0=1.0 if args.serve_storage == lbm.LBM_F16_SHIFTED else 0.0)
+    target = int(0.8 * len(cal))
+    while srv.stats()["completed"] < target:
+        time.sleep(0.01)
+    secs = srv.clock() - t0
+    srv.drain()
+    srv.close()
+    torch.cuda.empty_cache()
+    cap = target / secs
+    log(f"[serving] closed-loop capacity {cap:.1f} requests/s ({target} of {len(cal)} in {secs:.1f} s)")
+    return cap
+
+
 def run_serving(args, torch, lbm, inputs):
-    """Poisson trace, continuous batching vs the plain one-at-a-time path."""
-    trace = inputs.serving_trace(args.serve_requests, rate=args.serve_rate, seed=4,
+    """Poisson trace, continuous batching vs the plain one-at-a-time path.  The
+    arrival rate is --serve-rate, or (default) 1.1x the continuous path's
+    measured closed-loop capacity, so that the trace saturates the GPU."""
+    capacity = None
+    rate = args.serve_rate
+    if rate <= 0:
+        capacity = serving_capacity(args, torch, lbm, inputs)
+        rate = 1.1 * capacity
+    trace = inputs.serving_trace(args.serve_requests, rate=rate, seed=4,
                                  nmax=args.serve_nmax, smax=args.serve_smax)
-    res = {}
+    res = {"rate_req_s": rate, "capacity_req_s": capacity, "arrival_span_s": trace[-1].arrival}
     policies = ((lbm.LBM_POLICY_CONTINUOUS, "continuous"), (lbm.LBM_POLICY_FIFO, "fifo"))
     for policy, name in policies:
         if args.serve_policy not in ("both", name):
@@ -360,21 +392,34 @@ def run_serving(args, torch, lbm, inputs):
                 last = time.perf_counter()
                 log(f"[serving {name}] {srv.stats()['completed']} of {len(tickets)} done")
         srv.drain()
-        lat, done, unstable = [], [], 0
+        lat, lat_ok, done, unstable = [], [], [], 0
         for t in tickets:
             code, m = srv.poll(t)
             lat.append(m["t_done"] - m["t_submit"])
+            if code == lbm.LBM_OK:
+                lat_ok.append(lat[-1])
             done.append(m["t_done"])
             unstable += code != lbm.LBM_OK
         st = srv.stats()
         srv.close()
         lat.sort()
+        lat_ok.sort()
+
+        def pct(v, q):
+            return 1e3 * v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))]
+
         makespan = max(done) - t0
+        # Throughput counts the lattice updates of requests that completed
+        # LBM_OK; unstable requests are retired early and their work is listed
+        # apart.
         res[name] = {"requests": len(trace), "storage": ["f32", "f16_shifted", "f16_cell"][args.serve_storage],
                      "aggregate_mlups": st["lattice_updates"] / makespan / 1e6,
-                     "p50_ms": 1e3 * lat[len(lat) // 2],
-                     "p99_ms": 1e3 * lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+                     "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99),
+                     "ok_p50_ms": pct(lat_ok, 0.5), "ok_p99_ms": pct(lat_ok, 0.99),
                      "makespan_s": makespan, "unstable": unstable,
+                     "retired_early": st["retired_early"],
+                     "unstable_mlu": st["unstable_updates"] / 1e6,
+                     "ok_mlu": st["lattice_updates"] / 1e6,
                      "pool_high_water_gb": st["pool_high_water"] / 2**30}
         log(f"[serving {name}] {res[name]}")
         torch.cuda.empty_cache()
@@ -382,23 +427,51 @@ def run_serving(args, torch, lbm, inputs):
 
 
 def run_cpu_baseline(args, inputs):
-    """The FP64 oracle on the host cores, on a 512^2 window of the same workload."""
+    """The FP64 oracle on the host cores.  `value`: all host threads on a bounded
+    sample of the bench workload (a 512^2 window of the 4096^2 field, about
+    --cpu-seconds of work).  `legs`: one thread and all threads on that window,
+    on config 1 in full (64^2 droplet, 1000 steps) and on the 1024^2 droplet
+    truncated to 200 steps (its MLUPS stands for the 10000-step run, an
+    extrapolation)."""
     import oracle
-    n = 512
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
+    n = 512
     drops = inputs.many_droplets(args.n, args.drops, 8, 48, seed=3)
-    f = oracle.droplet_state(n, n, drops, seed=3, period=(args.n, args.n))
-    t0 = time.perf_counter()
-    f = oracle.step(f, args.G, args.tau, 20, threads)
-    probe = time.perf_counter() - t0
-    steps = max(20, int(20 * args.cpu_seconds / max(probe, 1e-3)))
-    t0 = time.perf_counter()
-    oracle.step(f, args.G, args.tau, steps, threads)
-    dt = time.perf_counter() - t0
-    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+    window = oracle.droplet_state(n, n, drops, seed=3, period=(args.n, args.n))
+
+    def timed(f, G, tau, steps, th):
+        t0 = time.perf_counter()
+        oracle.step(f, G, tau, steps, th)
+        return time.perf_counter() - t0
+
+    def window_rate(th, secs):
+        probe = timed(window, args.G, args.tau, 10, th)
+        steps = max(10, int(10 * secs / max(probe, 1e-3)))
+        dt = timed(window, args.G, args.tau, steps, th)
+        return steps, dt
+
+    steps, dt = window_rate(threads, args.cpu_seconds)
+    legs = [{"workload": f"many_droplets_{args.n} window {n}^2", "threads": threads, "steps": steps,
+             "seconds": dt, "mlups": n * n * steps / dt / 1e6}]
+    s1, d1 = window_rate(1, args.cpu_seconds / 2)
+    legs.append({"workload": f"many_droplets_{args.n} window {n}^2", "threads": 1, "steps": s1,
+                 "seconds": d1, "mlups": n * n * s1 / d1 / 1e6})
+    c1 = oracle.droplet_state(64, 64, inputs.single_droplet(64, 16), seed=1)
+    c2 = oracle.droplet_state(1024, 1024, inputs.single_droplet(1024, 200), seed=1)
+    for th in (1, threads):
+        d = timed(c1, -5.0, 1.0, 1000, th)
+        legs.append({"workload": "config1 64^2, 1000 steps (full)", "threads": th, "steps": 1000,
+                     "seconds": d, "mlups": 64 * 64 * 1000 / d / 1e6})
+        d = timed(c2, -5.0, 1.0, 200, th)
+        legs.append({"workload": "single_droplet_1024, 200 of 10000 steps (rate extrapolated)",
+                     "threads": th, "steps": 200, "seconds": d, "mlups": 1024 * 1024 * 200 / d / 1e6})
+    for leg in legs:
+        log(f"[cpu baseline] {leg['workload']}, {leg['threads']} threads: {leg['mlups']:.1f} MLUPS")
+    return {"value": legs[0]["mlups"], "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"FP64 oracle, {n}x{n} window of the 4096^2 2000-droplet field, {steps} steps, "
-                      f"{dt:.1f} s on {threads} host threads"}
+                      f"{dt:.1f} s on {threads} host threads",
+            "legs": legs}
 
 
 def main():
@@ -423,8 +496,11 @@ def main():
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--sweep-instances", type=int, default=512)
     ap.add_argument("--sweep-steps", type=int, default=4000)
-    ap.add_argument("--serve-requests", type=int, default=64)
-    ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="arrivals per second (default 0: 1.1x the measured closed-loop capacity)")
+    ap.add_argument("--serve-calib", type=int, default=400,
+                    help="requests of the closed-loop capacity calibration")
     ap.add_argument("--serve-nmax", type=int, default=2048)
     ap.add_argument("--serve-smax", type=int, default=20000)
     ap.add_argument("--serve-pool-gb", type=int, default=32)
@@ -483,7 +559,10 @@ def main():
                      "bytes_per_launch_per_cell": BYTES_F32,
                      "steps_per_launch": f32["steps_per_launch"],
                      "launch_ms": round(f32["launch_ms"], 5),
+                     # per update instead of per launch: MLUPS x 72 B / 8 TB/s (above 1
+                     # because a two-step launch moves each population once per two updates)
                      "over_one_step_roofline": round(f32["over_one_step_roofline"], 4),
+                     "frac_per_update": round(f32["over_one_step_roofline"], 4),
                      "one_step_kernel": one_step,
                      "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
         "f32": f32,

@@ -11,7 +11,7 @@
  *     collision towards the equilibrium at the force-shifted velocity
  *     u_eq = sum_i f_i e_i / rho + tau F / rho, and periodic streaming;
  *   - Sec. III-A: droplet in a square periodic domain;
- *   - Sec. II-D Eqs. (9)-(13), Sec. IV-F Eqs. (14)-(16): interface metrics.
+ *   - Sec. II-D Eqs. (9)-(13), Sec. IV-E Eqs. (14)-(16): interface metrics.
  *
  * Conventions shared by every entry point:
  *   - Velocities e0 = (0,0); e1..e4 = (1,0) (0,1) (-1,0) (0,-1);
@@ -173,7 +173,8 @@ lbm_status lbm_step_series(lbm_ctx* ctx, int64_t n, int32_t every, lbm_metrics* 
 
 /* Writes the macroscopic fields of the current state into caller device
  * arrays of nx * ny floats: rho = sum_i f_i and the half-force-corrected
- * velocity u = (sum_i f_i e_i + F / 2) / rho.  Any pointer may be NULL.
+ * velocity u = (sum_i f_i e_i + F / 2) / rho (the density and velocity fields
+ * that Sec. II-B, Eq. (2), takes as the fluid variables).  Any pointer may be NULL.
  * FP32.  Uses the idle population buffer as scratch.  Asynchronous. */
 lbm_status lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy);
 
@@ -185,12 +186,15 @@ lbm_status lbm_interface_metrics(lbm_ctx* ctx, lbm_metrics* out);
 
 /* Copies the current state out as 9 planes of nx * ny FP32 pre-collision
  * populations f_i(x, t) into a caller device buffer (FP16 storage is widened
- * exactly as the step kernel reads it).  Asynchronous. */
+ * exactly as the step kernel reads it).  With lbm_set_state it forks runs
+ * from one common state, as the protocol of Sec. III-C continues the pure
+ * LBM run and the coupled run from the same initialised droplet.
+ * Asynchronous. */
 lbm_status lbm_get_state(lbm_ctx* ctx, float* f);
 
 /* Replaces the current state with caller-supplied FP32 populations (same
  * layout as lbm_get_state), rounded to the storage type; the step counter is
- * kept.  Asynchronous. */
+ * kept (the fork of Sec. III-C).  Asynchronous. */
 lbm_status lbm_set_state(lbm_ctx* ctx, const float* f);
 
 /* Number of time steps taken since the last init / set_state-free creation. */
@@ -304,22 +308,37 @@ typedef struct lbm_result {
 typedef struct lbm_server_stats {
   int64_t submitted, admitted, completed, failed, queued, resident;
   int64_t ticks;
-  double lattice_updates;  /* sum over completed requests of nx*ny*steps */
-  size_t pool_bytes, pool_in_use, pool_high_water;
+  double lattice_updates;  /* sum over requests completed with LBM_OK of nx*ny*steps */
+  size_t pool_bytes;       /* bytes of the pool available to requests (the
+                              continuous policy keeps its batch tables in the
+                              rest) */
+  size_t pool_in_use, pool_high_water;
+  int64_t unstable;        /* requests completed with LBM_EUNSTABLE (also in failed) */
+  int64_t retired_early;   /* of those, retired before their last step */
+  double unstable_updates; /* lattice updates the unstable requests advanced */
 } lbm_server_stats;
 
 /* Starts a serving loop on a scheduler thread.  `pool` (caller device buffer
  * of pool_bytes, 256-byte aligned) is the HBM budget: each admitted request's
  * two population buffers and workspace are carved out of it and returned on
- * completion.  Requests are admitted first-come first-served, except that a
- * request that does not fit yet may be passed by a later one that does.
- * Admitted requests are initialised and advanced together.  With
- * fake_executor = 1, pool may be NULL and no GPU is used. */
+ * completion; the continuous policy keeps its batch tables at the top of the
+ * pool (lbm_server_stats.pool_bytes gives what is left for requests).
+ * Requests are admitted first-come first-served, except that a request that
+ * does not fit yet may be passed by a later one that does.  Admitted requests
+ * are initialised and advanced together.  A run whose step kernels meet a cell
+ * with a non-finite or non-positive density is retired within a tick or two,
+ * before its last step, and completes with LBM_EUNSTABLE (its result's
+ * metrics.step is where it stopped).  With fake_executor = 1, pool may be
+ * NULL and no GPU is used; a request whose starting density is not positive
+ * then stands for an unstable run and is retired after its first tick. */
 lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
                              const lbm_server_opts* opts, lbm_server** out);
 
-/* Queues a request; thread-safe.  LBM_EINVAL for bad parameters, LBM_ENOMEM
- * if the request alone exceeds the pool. */
+/* Queues a request; thread-safe.  LBM_EINVAL for bad parameters (checked
+ * before any host array is read: n_drops must fit the grid's scratch, as in
+ * lbm_init_droplets), LBM_ENOMEM if the request alone exceeds the pool's
+ * capacity for requests, LBM_EDEVICE if the scheduler has stopped on an
+ * internal error. */
 lbm_status lbm_submit(lbm_server* s, const lbm_request* r, uint64_t* ticket);
 
 /* Non-blocking: LBM_PENDING, or LBM_OK / LBM_EUNSTABLE with *out filled (the

@@ -2,9 +2,10 @@
 
 TEST INFRASTRUCTURE ONLY (see ``oracle/__init__.py``).
 
-The pseudopotential force of Sec. II-A of Li & Zhang (arXiv 2504.10539)
-"induces a non-ideal equation of state".  With the D2Q9 weights and
-psi = 1 - exp(-rho) that EOS is
+In the pseudopotential model of Sec. II-A of Li & Zhang (arXiv 2504.10539)
+the interaction force turns the ideal-gas pressure into a non-ideal one, which
+is what lets two phases coexist.  With the D2Q9 weights and psi = 1 - exp(-rho)
+that equation of state is
 
     p(rho) = rho / 3 + G psi(rho)^2 / 6                      (c_s^2 = 1/3)
 

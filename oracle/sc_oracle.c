@@ -17,7 +17,7 @@
  *     D2Q9, psi = 1 - exp(-rho), F = -G psi(x) sum_i w_i psi(x + e_i) e_i,
  *     BGK collision with the Shan-Chen velocity shift u_eq = u' + tau F / rho.
  *   - Sec. III-A: square domain with periodic boundaries; droplet set-up.
- *   - Sec. II-D, Eqs. (9)-(13) and Sec. IV-F, Eqs. (14)-(16): interface width,
+ *   - Sec. II-D, Eqs. (9)-(13) and Sec. IV-E, Eqs. (14)-(16): interface width,
  *     maximum gradient, phase separation, effective width, interface energy,
  *     with the central-difference gradient of Eq. (16).
  *

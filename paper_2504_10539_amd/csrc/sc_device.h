@@ -34,7 +34,11 @@ struct InstDesc {
   int64_t steps;      // batched runs: steps taken
   int32_t storage;
   int32_t two_step;   // batched runs: advanced by two-step launches (and a tail)
-  int32_t pad[2];
+  // Address of a 32-bit status word that a step kernel sets to 1 when it
+  // meets a cell whose density is not finite or not positive (0: no word).
+  // The serving loop points it at pinned host memory and retires such a run
+  // early instead of stepping it to the end.
+  uint64_t flag;
 };
 static_assert(sizeof(InstDesc) == 80, "InstDesc layout");
 
@@ -209,6 +213,24 @@ __device__ __forceinline__ void momentum(const float f[9], float& jx, float& jy)
 __device__ __forceinline__ float recip(float x) {
   const float r = __builtin_amdgcn_rcpf(x);
   return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+
+// Divergence check of a collided cell: the lanes (of this wavefront) whose
+// density is NaN, infinite, zero or negative, among the lanes where `live`
+// holds.  One class test per cell (mask: signalling and quiet NaN, -inf,
+// negative normal and subnormal, -0, +0, +inf).
+constexpr int kUnstableClass = 0x27F;
+__device__ __forceinline__ uint64_t unstable_lanes(float rho, bool live) {
+  return __builtin_amdgcn_ballot_w64(live && __builtin_amdgcn_classf(rho, kUnstableClass));
+}
+// Sets the run's status word if this wavefront met an unstable cell.  Called
+// once per work item with every lane active; the store is a plain vector store
+// of the same value from each such wavefront.
+__device__ __forceinline__ void report_unstable(const InstDesc* dp, uint64_t bad) {
+  if (bad != 0 && (threadIdx.x & 63) == 0) {
+    const uint64_t a = dp->flag;
+    if (a != 0) *reinterpret_cast<volatile int*>(a) = 1;
+  }
 }
 
 // BGK collision with the Shan-Chen velocity shift, in place on f:

@@ -1,6 +1,6 @@
 // sc_kernels.hip -- gfx950 kernels of the D2Q9 Shan-Chen step and its
 // diagnostics (Li & Zhang, arXiv 2504.10539: Sec. II-A Eq. (1); Sec. III-A
-// initial droplet; Sec. II-D Eqs. (9)-(13) and Sec. IV-F Eqs. (14)-(16)).
+// initial droplet; Sec. II-D Eqs. (9)-(13) and Sec. IV-E Eqs. (14)-(16)).
 //
 // Population buffers hold the nine populations structure-of-arrays, in the
 // layout of row_index() (sc_device.h).  A buffer holds post-collision values
@@ -97,6 +97,7 @@ struct Strip {
   int xc[CPT + 1], xm[CPT + 1], xp[CPT + 1];
   bool live[CPT + 1];
   float G, tau, omega;
+  uint64_t bad;  // lanes that collided a cell with a non-finite or non-positive density
   // DIAG accumulators: mass, mom_x, mom_y, bad cells, cells above the
   // threshold, max |grad rho|, sum |grad rho|, sum |grad rho|^2, rho max, min.
   double acc[10];
@@ -132,6 +133,7 @@ struct Strip {
     h = ti.h;
     dir = ti.dir;
     wcols = min(SW, nx - x0);
+    bad = 0;
     G = dp->G;
     tau = dp->tau;
     omega = dp->omega;
@@ -287,6 +289,7 @@ struct Strip {
       float Fx, Fy;
       force_of(md[c], md[c + 1], up[c], md[c - 1], dn[c], up[c + 1], up[c - 1], dn[c - 1],
                dn[c + 1], G, Fx, Fy);
+      bad |= unstable_lanes(f[k][9], true);
       collide(f[k], f[k][9], Fx, Fy, tau, omega);
       const uint32_t xb = fresh((uint32_t)xc[k] * (uint32_t)sizeof(T));
       if constexpr (S::kCellShift) {
@@ -379,6 +382,7 @@ __global__ __launch_bounds__(NT) void k_step(const InstDesc* __restrict__ descs,
       St s;
       s.setup(dp, ti, sub);
       march<St, PF>(s, ring);
+      report_unstable(dp, s.bad);
     }
     __syncthreads();  // the next item reuses the ring
   }
@@ -408,6 +412,7 @@ __global__ __launch_bounds__(kDiagThreads) void k_step_diag(const InstDesc* __re
     s.setup(dp, ti, sub);
     s.diag_zero();
     march<St, 2>(s, ring, rring);
+    report_unstable(dp, s.bad);
     block_reduce<10>(s.acc, op);
     if (threadIdx.x == 0)
       for (int q = 0; q < 10; ++q) partials[(size_t)it * kPartialStride + q] = s.acc[q];
@@ -558,6 +563,7 @@ struct PairStrip {
   uint32_t pb;  // byte offset of this lane's pair within a row
   bool out_ok;  // this lane writes its pair
   float G, tau, omega;
+  uint64_t bad;  // lanes that collided a cell with a non-finite or non-positive density
 
   __device__ __forceinline__ static uint64_t uniform(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -613,6 +619,7 @@ struct PairStrip {
     c = c < 0 ? c + nx : (c >= nx ? c - nx : c);
     pb = (uint32_t)c * (uint32_t)sizeof(T);
     out_ok = lane >= 1 && lane <= 62 && 2 * (lane - 1) < wcols;
+    bad = 0;
   }
 
   __device__ __forceinline__ int row_of(int j) const {
@@ -701,11 +708,12 @@ struct PairStrip {
   // Collide the pair at march position r and store it.  Marching upwards the
   // previous position is the row above.
   __device__ __forceinline__ void finish(int r, float (&fa)[9], float (&fb)[9], const PsiRow& prev,
-                                         const PsiRow& md, const PsiRow& next) const {
+                                         const PsiRow& md, const PsiRow& next) {
     const PsiRow& dn = dir ? next : prev;
     const PsiRow& up = dir ? prev : next;
     float Fx, Fy;
     force_of(md.a, md.b, up.a, md.l, dn.a, up.b, up.l, dn.l, dn.b, G, Fx, Fy);
+    bad |= unstable_lanes(md.rho_a, out_ok) | unstable_lanes(md.rho_b, out_ok);
     collide(fa, md.rho_a, Fx, Fy, tau, omega);
     force_of(md.b, md.r, up.b, md.a, dn.b, up.r, up.a, dn.a, dn.r, G, Fx, Fy);
     collide(fb, md.rho_b, Fx, Fy, tau, omega);
@@ -783,6 +791,7 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
         if (pos(fa0, fb0, fa1, fb1, w1, w0, p1, p2, p0)) break;
         if (pos(fa1, fb1, fa0, fb0, w0, w1, p2, p0, p1)) break;
       }
+      report_unstable(dp, s.bad);
     }
   }
 }
@@ -1072,6 +1081,7 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
       F s;
       s.setup(dp, ti, sub);
       const int h = s.h;
+      uint64_t bad = 0;  // lanes that collided a cell with a non-finite or non-positive density
       // With constant ring slots the march is instantiated per direction, so
       // that every ring access is the lane's LDS address plus a constant.  In
       // march order the row below a row (y - 1) is the previous one when
@@ -1161,6 +1171,7 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         if constexpr (!kLead) {
           float Fx, Fy;
           ring_force(psb[ring(below)], psb[ring(0)], psb[ring(-below)], tf, tfl, tfr, s.G, Fx, Fy);
+          bad |= unstable_lanes(fb_p[9], s.out);
           collide(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
           s.store(j, fb_p);
         }
@@ -1190,6 +1201,7 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         go(std::true_type{});
       else
         go(std::false_type{});
+      report_unstable(dp, bad);
     }
     if constexpr (DIAG) {
       block_reduce<10>(acc, op);
@@ -1849,9 +1861,13 @@ hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs&
   });
 }
 
+int diagnostics_blocks(int nx, int ny) {
+  return grid_for((size_t)nx * ny, kRedThreads, kMaxPartials);
+}
+
 hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, float rho0,
                               double* rho64, double* partials, double* out, hipStream_t st) {
-  const int g = grid_for((size_t)nx * ny, kRedThreads, kMaxPartials);
+  const int g = diagnostics_blocks(nx, ny);
   const hipError_t e = with_storage(storage, [&](auto tag) {
     using S = decltype(tag);
     hipLaunchKernelGGL(k_diag_rho<S>, dim3(g), dim3(kRedThreads), 0, st, (const typename S::T*)src,

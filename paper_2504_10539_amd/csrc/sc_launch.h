@@ -67,6 +67,9 @@ hipError_t launch_set_state(int storage, const float* f, int nx, int ny, float r
                             hipStream_t st);
 hipError_t launch_init(int storage, const double* drops, int nd, const InitArgs& a, double* rho64,
                        float rho0, void* dst, hipStream_t st);
+// Blocks of the diagnostics pass on an nx x ny grid (partial records it
+// writes; at most kMaxPartials).
+int diagnostics_blocks(int nx, int ny);
 // Writes {mass, mom_x, mom_y, bad, n_above, Gmax, sum_grad, sum_grad2, rho_max, rho_min} to out.
 hipError_t launch_diagnostics(int storage, const void* src, int nx, int ny, float rho0,
                               double* rho64, double* partials, double* out, hipStream_t st);

@@ -30,6 +30,15 @@ lbm_status fail(lbm_status code, const std::string& msg) {
   return code;
 }
 
+lbm_status fail_nothrow(lbm_status code, const char* where, const char* what) noexcept {
+  try {
+    g_error = std::string(where) + ": " + what;
+  } catch (...) {
+    g_error.clear();
+  }
+  return code;
+}
+
 lbm_status hip_fail(hipError_t e, const char* what) {
   g_error = std::string(what) + ": " + hipGetErrorString(e);
   return LBM_EDEVICE;
@@ -330,6 +339,7 @@ InstDesc lbm_ctx::host_desc() const {
   d.parity = 0;
   d.nsub = INT32_MAX;
   d.storage = p.storage;
+  d.flag = reinterpret_cast<uint64_t>(flag);
   return d;
 }
 
@@ -840,7 +850,7 @@ BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) {
 // run's own are not uploaded, so creating it does not wait for the stream.
 lbm_status sclbm::create_ctx(const lbm_params* p, void* popA, void* popB, size_t pop_bytes,
                              void* work, size_t work_bytes, void* hip_stream, bool standalone,
-                             lbm_ctx** out) {
+                             lbm_ctx** out, int* flag) {
   if (!out) return fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
   lbm_status s = validate_params(p);
@@ -861,6 +871,7 @@ lbm_status sclbm::create_ctx(const lbm_params* p, void* popA, void* popB, size_t
   c->work = work;
   c->work_bytes = work_bytes;
   c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  c->flag = flag;
   c->lay = lay;
   char* w = reinterpret_cast<char*>(work);
   c->d_desc = reinterpret_cast<InstDesc*>(w + lay.desc);
@@ -958,78 +969,98 @@ const char* lbm_last_error(void) { return g_error.c_str(); }
 const char* lbm_version(void) { return "sclbm 0.1 (gfx950)"; }
 
 lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes) {
-  const lbm_status s = validate_params(p);
-  if (s != LBM_OK) return s;
-  if (pop_bytes) *pop_bytes = pop_bytes_for(*p);
-  if (work_bytes) *work_bytes = work_layout(p->nx, p->ny).total;
-  return LBM_OK;
+  return guarded("lbm_buffer_bytes", [&]() -> lbm_status {
+    const lbm_status s = validate_params(p);
+    if (s != LBM_OK) return s;
+    if (pop_bytes) *pop_bytes = pop_bytes_for(*p);
+    if (work_bytes) *work_bytes = work_layout(p->nx, p->ny).total;
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_create(const lbm_params* p, void* popA, void* popB, size_t pop_bytes, void* work,
                       size_t work_bytes, void* hip_stream, lbm_ctx** out) {
-  return sclbm::create_ctx(p, popA, popB, pop_bytes, work, work_bytes, hip_stream, true, out);
+  return guarded("lbm_create", [&]() -> lbm_status {
+    return sclbm::create_ctx(p, popA, popB, pop_bytes, work, work_bytes, hip_stream, true, out);
+  });
 }
 
 lbm_status lbm_destroy(lbm_ctx* c) {
-  if (!c) return LBM_OK;
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  const hipError_t e = hipStreamSynchronize(c->stream);
-  if (c->h_result) (void)hipHostFree(c->h_result);
-  if (c->h_series) (void)hipHostFree(c->h_series);
-  delete c;
-  return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+  return guarded("lbm_destroy", [&]() -> lbm_status {
+    if (!c) return LBM_OK;
+    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+    const hipError_t e = hipStreamSynchronize(c->stream);
+    if (c->h_result) (void)hipHostFree(c->h_result);
+    if (c->h_series) (void)hipHostFree(c->h_series);
+    delete c;
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+  });
 }
 
 lbm_status lbm_init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip) {
-  return sclbm::init_droplets(c, drops, n, ip, true);
+  return guarded("lbm_init_droplets", [&]() -> lbm_status {
+    return sclbm::init_droplets(c, drops, n, ip, true);
+  });
 }
 
 lbm_status lbm_step_n(lbm_ctx* c, int64_t n) {
-  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-  return c->advance(n);
+  return guarded("lbm_step_n", [&]() -> lbm_status {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    return c->advance(n);
+  });
 }
 
 lbm_status lbm_step_series(lbm_ctx* c, int64_t n, int32_t every, lbm_metrics* out,
                            int32_t capacity, int32_t* count) {
-  if (!c || !count) return fail(LBM_EINVAL, "ctx or count is NULL");
-  *count = 0;
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  if (n < 0 || every < 1) return fail(LBM_EINVAL, "need n >= 0 and every >= 1");
-  const int64_t need = (n + every - 1) / every;
-  if (need > capacity || (need > 0 && !out))
-    return fail(LBM_EINVAL, "out holds fewer than ceil(n / every) records");
-  return c->step_series(n, every, out, count);
+  return guarded("lbm_step_series", [&]() -> lbm_status {
+    if (!c || !count) return fail(LBM_EINVAL, "ctx or count is NULL");
+    *count = 0;
+    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+    if (n < 0 || every < 1) return fail(LBM_EINVAL, "need n >= 0 and every >= 1");
+    const int64_t need = (n + every - 1) / every;
+    if (need > capacity || (need > 0 && !out))
+      return fail(LBM_EINVAL, "out holds fewer than ceil(n / every) records");
+    return c->step_series(n, every, out, count);
+  });
 }
 
 lbm_status lbm_moments(lbm_ctx* c, float* rho, float* ux, float* uy) {
-  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-  if (!rho && !ux && !uy) return LBM_OK;
-  float* r = rho ? rho : reinterpret_cast<float*>(c->pop[c->parity ^ 1]);
-  SCLBM_HIP(launch_moments(c->p.storage, c->pop[c->parity], c->p.nx, c->p.ny, c->host_desc().rho0,
-                           (float)c->p.G, r, ux, uy, c->stream));
-  return LBM_OK;
+  return guarded("lbm_moments", [&]() -> lbm_status {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!rho && !ux && !uy) return LBM_OK;
+    float* r = rho ? rho : reinterpret_cast<float*>(c->pop[c->parity ^ 1]);
+    SCLBM_HIP(launch_moments(c->p.storage, c->pop[c->parity], c->p.nx, c->p.ny, c->host_desc().rho0,
+                             (float)c->p.G, r, ux, uy, c->stream));
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_interface_metrics(lbm_ctx* c, lbm_metrics* out) {
-  if (!c || !out) return fail(LBM_EINVAL, "ctx or out is NULL");
-  return c->diagnostics(out);
+  return guarded("lbm_interface_metrics", [&]() -> lbm_status {
+    if (!c || !out) return fail(LBM_EINVAL, "ctx or out is NULL");
+    return c->diagnostics(out);
+  });
 }
 
 lbm_status lbm_get_state(lbm_ctx* c, float* f) {
-  if (!c || !f) return fail(LBM_EINVAL, "ctx or buffer is NULL");
-  SCLBM_HIP(launch_get_state(c->p.storage, c->pop[c->parity], c->p.nx, c->p.ny,
-                             c->host_desc().rho0, f, c->stream));
-  return LBM_OK;
+  return guarded("lbm_get_state", [&]() -> lbm_status {
+    if (!c || !f) return fail(LBM_EINVAL, "ctx or buffer is NULL");
+    SCLBM_HIP(launch_get_state(c->p.storage, c->pop[c->parity], c->p.nx, c->p.ny,
+                               c->host_desc().rho0, f, c->stream));
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_set_state(lbm_ctx* c, const float* f) {
-  if (!c || !f) return fail(LBM_EINVAL, "ctx or buffer is NULL");
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  SCLBM_HIP(launch_set_state(c->p.storage, f, c->p.nx, c->p.ny, c->host_desc().rho0,
-                             c->pop[c->parity], c->stream));
-  return LBM_OK;
+  return guarded("lbm_set_state", [&]() -> lbm_status {
+    if (!c || !f) return fail(LBM_EINVAL, "ctx or buffer is NULL");
+    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+    SCLBM_HIP(launch_set_state(c->p.storage, f, c->p.nx, c->p.ny, c->host_desc().rho0,
+                               c->pop[c->parity], c->stream));
+    return LBM_OK;
+  });
 }
 
 int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
@@ -1038,232 +1069,254 @@ int32_t lbm_tile_count(void) { return kNumTiles; }
 
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
                              int32_t* prefetch, int32_t* cells, int32_t* paired, int32_t* steps) {
-  if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
-  const StepVariant& v = step_variant(tile_variant(k));
-  if (width) *width = tile_width(k);
-  if (rows) *rows = tile_rows(k);
-  if (threads) *threads = v.threads;
-  if (prefetch) *prefetch = v.prefetch;
-  if (cells) *cells = v.cells;
-  if (paired) *paired = v.paired;
-  if (steps) *steps = v.steps;
-  return LBM_OK;
+  return guarded("lbm_tile_describe", [&]() -> lbm_status {
+    if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+    const StepVariant& v = step_variant(tile_variant(k));
+    if (width) *width = tile_width(k);
+    if (rows) *rows = tile_rows(k);
+    if (threads) *threads = v.threads;
+    if (prefetch) *prefetch = v.prefetch;
+    if (cells) *cells = v.cells;
+    if (paired) *paired = v.paired;
+    if (steps) *steps = v.steps;
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_default_tile(const lbm_params* p, int32_t* k) {
-  const lbm_status v = validate_params(p);
-  if (v != LBM_OK) return v;
-  if (!k) return fail(LBM_EINVAL, "k is NULL");
-  *k = default_tile(*p);
-  return LBM_OK;
+  return guarded("lbm_default_tile", [&]() -> lbm_status {
+    const lbm_status v = validate_params(p);
+    if (v != LBM_OK) return v;
+    if (!k) return fail(LBM_EINVAL, "k is NULL");
+    *k = default_tile(*p);
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_tile_layout(const lbm_params* p, int32_t k, int32_t* rows, int32_t* items) {
-  const lbm_status v = validate_params(p);
-  if (v != LBM_OK) return v;
-  if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
-  const int r = band_rows(k, p->nx, p->ny, p->storage);
-  const int w = strip_width(k, p->nx);
-  if (rows) *rows = r;
-  if (items) *items = ((p->nx + w - 1) / w) * ((p->ny + r - 1) / r);
-  return LBM_OK;
+  return guarded("lbm_tile_layout", [&]() -> lbm_status {
+    const lbm_status v = validate_params(p);
+    if (v != LBM_OK) return v;
+    if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+    const int r = band_rows(k, p->nx, p->ny, p->storage);
+    const int w = strip_width(k, p->nx);
+    if (rows) *rows = r;
+    if (items) *items = ((p->nx + w - 1) / w) * ((p->ny + r - 1) / r);
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
-  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-  if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
-  if (!tile_valid(k, c->p.nx))
-    return fail(LBM_EINVAL, "paired-column tile shapes need an even nx >= 128");
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  return c->upload_tile(k);
+  return guarded("lbm_set_tile", [&]() -> lbm_status {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
+    if (!tile_valid(k, c->p.nx))
+      return fail(LBM_EINVAL, "paired-column tile shapes need an even nx >= 128");
+    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+    return c->upload_tile(k);
+  });
 }
 
 int32_t lbm_get_tile(const lbm_ctx* c) { return c ? c->tile : -1; }
 
 lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
-  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
-  hipEvent_t e0, e1;
-  SCLBM_HIP(hipEventCreate(&e0));
-  SCLBM_HIP(hipEventCreate(&e1));
-  int best = c->tile;
-  double best_ms = 1e300;
-  lbm_status st = LBM_OK;
-  for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
-    if (!tile_valid(k, c->p.nx)) continue;
-    st = c->upload_tile(k);
-    if (st != LBM_OK) break;
-    const int v = tile_variant(k);
-    // Read the current buffer and write the idle one, leaving the state as is.
-    hipError_t e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
-                               c->parity, c->stream);
-    if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r)
-      e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems, c->parity,
-                      c->stream);
-    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      st = hip_fail(e, "autotune launch");
-      break;
+  return guarded("lbm_autotune", [&]() -> lbm_status {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+    if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+    hipEvent_t e0, e1;
+    SCLBM_HIP(hipEventCreate(&e0));
+    SCLBM_HIP(hipEventCreate(&e1));
+    int best = c->tile;
+    double best_ms = 1e300;
+    lbm_status st = LBM_OK;
+    for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+      if (!tile_valid(k, c->p.nx)) continue;
+      st = c->upload_tile(k);
+      if (st != LBM_OK) break;
+      const int v = tile_variant(k);
+      // Read the current buffer and write the idle one, leaving the state as is.
+      hipError_t e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
+                                 c->parity, c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems, c->parity,
+                        c->stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "autotune launch");
+        break;
+      }
+      const double per = ms / reps / tile_steps(k);  // per time step
+      if (per < best_ms) {
+        best_ms = per;
+        best = k;
+      }
     }
-    const double per = ms / reps / tile_steps(k);  // per time step
-    if (per < best_ms) {
-      best_ms = per;
-      best = k;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st != LBM_OK) return st;
-  st = c->upload_tile(best);
-  if (st != LBM_OK) return st;
-  record_tuned_tile(c->p, c->arch, best, best_ms);
-  if (best_out) *best_out = best;
-  return LBM_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != LBM_OK) return st;
+    st = c->upload_tile(best);
+    if (st != LBM_OK) return st;
+    record_tuned_tile(c->p, c->arch, best, best_ms);
+    if (best_out) *best_out = best;
+    return LBM_OK;
+  });
 }
 
 // ------------------------------------------------------------------ batch C-ABI
 
 lbm_status lbm_batch_work_bytes(lbm_ctx* const* ctxs, int32_t n, size_t* bytes) {
-  if (!ctxs || n < 1 || !bytes) return fail(LBM_EINVAL, "bad batch arguments");
-  std::vector<lbm_ctx*> m(ctxs, ctxs + n);
-  for (lbm_ctx* c : m)
-    if (!c) return fail(LBM_EINVAL, "NULL context in batch");
-  const BatchShape b = batch_shape_max(m);
-  *bytes = BatchEngine::work_bytes(n, b.items, b.titems, kMaxGraphSteps);
-  return LBM_OK;
+  return guarded("lbm_batch_work_bytes", [&]() -> lbm_status {
+    if (!ctxs || n < 1 || !bytes) return fail(LBM_EINVAL, "bad batch arguments");
+    std::vector<lbm_ctx*> m(ctxs, ctxs + n);
+    for (lbm_ctx* c : m)
+      if (!c) return fail(LBM_EINVAL, "NULL context in batch");
+    const BatchShape b = batch_shape_max(m);
+    *bytes = BatchEngine::work_bytes(n, b.items, b.titems, kMaxGraphSteps);
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_batch_create(lbm_ctx* const* ctxs, int32_t n, void* work, size_t work_bytes,
                             int32_t steps_per_graph, lbm_batch** out) {
-  if (!out) return fail(LBM_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!ctxs || n < 1 || !work) return fail(LBM_EINVAL, "bad batch arguments");
-  if (steps_per_graph < 1 || steps_per_graph > kMaxGraphSteps)
-    return fail(LBM_EINVAL, "steps_per_graph must be in [1, " + std::to_string(kMaxGraphSteps) + "]");
-  if ((uintptr_t)work & 255) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
-  std::vector<lbm_ctx*> m(ctxs, ctxs + n);
-  for (size_t i = 0; i < m.size(); ++i) {
-    if (!m[i]) return fail(LBM_EINVAL, "NULL context in batch");
-    if (m[i]->batch) return fail(LBM_EBUSY, "context already belongs to a batch");
-    if (m[i]->stream != m[0]->stream) return fail(LBM_EINVAL, "batch members need one stream");
-    for (size_t j = 0; j < i; ++j)
-      if (m[j] == m[i]) return fail(LBM_EINVAL, "context listed twice");
-  }
-  const BatchShape shape = batch_shape(m);
-  lbm_batch* b = new (std::nothrow) lbm_batch();
-  if (!b) return fail(LBM_ENOMEM, "host allocation failed");
-  b->members = m;
-  b->work = work;
-  b->work_bytes = work_bytes;
-  b->K = steps_per_graph;
-  lbm_status st = b->eng.init(m[0]->stream, steps_per_graph, n, shape.items, shape.titems,
-                              shape.variants, work, work_bytes);
-  if (st == LBM_OK) st = b->eng.load(m, std::vector<int64_t>(m.size(), 0));
-  if (st != LBM_OK) {
-    b->eng.destroy();
-    delete b;
-    return st;
-  }
-  for (lbm_ctx* c : m) c->batch = b;
-  *out = b;
-  return LBM_OK;
+  return guarded("lbm_batch_create", [&]() -> lbm_status {
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || n < 1 || !work) return fail(LBM_EINVAL, "bad batch arguments");
+    if (steps_per_graph < 1 || steps_per_graph > kMaxGraphSteps)
+      return fail(LBM_EINVAL, "steps_per_graph must be in [1, " + std::to_string(kMaxGraphSteps) + "]");
+    if ((uintptr_t)work & 255) return fail(LBM_EINVAL, "workspace must be 256-byte aligned");
+    std::vector<lbm_ctx*> m(ctxs, ctxs + n);
+    for (size_t i = 0; i < m.size(); ++i) {
+      if (!m[i]) return fail(LBM_EINVAL, "NULL context in batch");
+      if (m[i]->batch) return fail(LBM_EBUSY, "context already belongs to a batch");
+      if (m[i]->stream != m[0]->stream) return fail(LBM_EINVAL, "batch members need one stream");
+      for (size_t j = 0; j < i; ++j)
+        if (m[j] == m[i]) return fail(LBM_EINVAL, "context listed twice");
+    }
+    const BatchShape shape = batch_shape(m);
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return fail(LBM_ENOMEM, "host allocation failed");
+    b->members = m;
+    b->work = work;
+    b->work_bytes = work_bytes;
+    b->K = steps_per_graph;
+    lbm_status st = b->eng.init(m[0]->stream, steps_per_graph, n, shape.items, shape.titems,
+                                shape.variants, work, work_bytes);
+    if (st == LBM_OK) st = b->eng.load(m, std::vector<int64_t>(m.size(), 0));
+    if (st != LBM_OK) {
+      b->eng.destroy();
+      delete b;
+      return st;
+    }
+    for (lbm_ctx* c : m) c->batch = b;
+    *out = b;
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_batch_step_n(lbm_batch* b, int64_t n) {
-  if (!b) return fail(LBM_EINVAL, "batch is NULL");
-  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-  if (n == 0) return LBM_OK;
-  lbm_status st = b->eng.arm(n);
-  const int64_t replays = (n + b->eng.K - 1) / b->eng.K;
-  for (int64_t r = 0; r < replays && st == LBM_OK; ++r) st = b->eng.replay();
-  if (st != LBM_OK) return st;
-  const int64_t K = b->eng.K;
-  for (lbm_ctx* c : b->members) {
-    const bool two = b->eng.two_step(c->p.storage);
-    const int64_t flips = (n / K) * tick_flips(K, two) + tick_flips(n % K, two);
-    c->steps += n;
-    c->parity = (int)((c->parity + flips) & 1);
-  }
-  return LBM_OK;
+  return guarded("lbm_batch_step_n", [&]() -> lbm_status {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+    if (n == 0) return LBM_OK;
+    lbm_status st = b->eng.arm(n);
+    const int64_t replays = (n + b->eng.K - 1) / b->eng.K;
+    for (int64_t r = 0; r < replays && st == LBM_OK; ++r) st = b->eng.replay();
+    if (st != LBM_OK) return st;
+    const int64_t K = b->eng.K;
+    for (lbm_ctx* c : b->members) {
+      const bool two = b->eng.two_step(c->p.storage);
+      const int64_t flips = (n / K) * tick_flips(K, two) + tick_flips(n % K, two);
+      c->steps += n;
+      c->parity = (int)((c->parity + flips) & 1);
+    }
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
-  if (!b) return fail(LBM_EINVAL, "batch is NULL");
-  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
-  hipEvent_t e0, e1;
-  SCLBM_HIP(hipEventCreate(&e0));
-  SCLBM_HIP(hipEventCreate(&e1));
-  int best = -1;
-  double best_ms = 1e300;
-  lbm_status st = LBM_OK;
-  for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
-    bool valid = true;
-    for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx);
-    if (!valid) continue;
-    // Every member takes one step (two with a two-step shape) per launch from
-    // its current buffer into its idle one, and the descriptors are not
-    // advanced: the state is unchanged.  Compared per time step.
-    const int per = tile_steps(k);
-    st = batch_rebuild(b, k, per);
-    if (st == LBM_ENOMEM) {  // this shape's tables do not fit the workspace
-      st = LBM_OK;
-      continue;
+  return guarded("lbm_batch_autotune", [&]() -> lbm_status {
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+    hipEvent_t e0, e1;
+    SCLBM_HIP(hipEventCreate(&e0));
+    SCLBM_HIP(hipEventCreate(&e1));
+    int best = -1;
+    double best_ms = 1e300;
+    lbm_status st = LBM_OK;
+    for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+      bool valid = true;
+      for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx);
+      if (!valid) continue;
+      // Every member takes one step (two with a two-step shape) per launch from
+      // its current buffer into its idle one, and the descriptors are not
+      // advanced: the state is unchanged.  Compared per time step.
+      const int per = tile_steps(k);
+      st = batch_rebuild(b, k, per);
+      if (st == LBM_ENOMEM) {  // this shape's tables do not fit the workspace
+        st = LBM_OK;
+        continue;
+      }
+      if (st != LBM_OK) break;
+      BatchEngine& g = b->eng;
+      auto launch_all = [&]() {
+        hipError_t e = hipSuccess;
+        for (int s = 0; s < kNumStorages && e == hipSuccess; ++s)
+          if (g.grid[s] > 0)
+            e = launch_step(s, g.variant[s], g.d_desc, g.d_items[s], g.d_nitems[s], g.grid[s], 0,
+                            g.stream);
+        return e;
+      };
+      hipError_t e = launch_all();
+      if (e == hipSuccess) e = hipEventRecord(e0, g.stream);
+      for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_all();
+      if (e == hipSuccess) e = hipEventRecord(e1, g.stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        st = hip_fail(e, "batch autotune launch");
+        break;
+      }
+      if (ms / reps / per < best_ms) {
+        best_ms = ms / reps / per;
+        best = k;
+      }
     }
-    if (st != LBM_OK) break;
-    BatchEngine& g = b->eng;
-    auto launch_all = [&]() {
-      hipError_t e = hipSuccess;
-      for (int s = 0; s < kNumStorages && e == hipSuccess; ++s)
-        if (g.grid[s] > 0)
-          e = launch_step(s, g.variant[s], g.d_desc, g.d_items[s], g.d_nitems[s], g.grid[s], 0,
-                          g.stream);
-      return e;
-    };
-    hipError_t e = launch_all();
-    if (e == hipSuccess) e = hipEventRecord(e0, g.stream);
-    for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_all();
-    if (e == hipSuccess) e = hipEventRecord(e1, g.stream);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) {
-      st = hip_fail(e, "batch autotune launch");
-      break;
-    }
-    if (ms / reps / per < best_ms) {
-      best_ms = ms / reps / per;
-      best = k;
-    }
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (st == LBM_OK && best < 0) st = fail(LBM_ENOMEM, "no tile shape fits the batch workspace");
-  const lbm_status r = batch_rebuild(b, st == LBM_OK ? best : -1, 0);
-  if (st != LBM_OK) return st;
-  if (r != LBM_OK) return r;
-  if (best_out) *best_out = best;
-  return LBM_OK;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == LBM_OK && best < 0) st = fail(LBM_ENOMEM, "no tile shape fits the batch workspace");
+    const lbm_status r = batch_rebuild(b, st == LBM_OK ? best : -1, 0);
+    if (st != LBM_OK) return st;
+    if (r != LBM_OK) return r;
+    if (best_out) *best_out = best;
+    return LBM_OK;
+  });
 }
 
 lbm_status lbm_batch_destroy(lbm_batch* b) {
-  if (!b) return LBM_OK;
-  const hipError_t e = hipStreamSynchronize(b->eng.stream);
-  for (lbm_ctx* c : b->members) c->batch = nullptr;
-  b->eng.destroy();
-  delete b;
-  return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+  return guarded("lbm_batch_destroy", [&]() -> lbm_status {
+    if (!b) return LBM_OK;
+    const hipError_t e = hipStreamSynchronize(b->eng.stream);
+    for (lbm_ctx* c : b->members) c->batch = nullptr;
+    b->eng.destroy();
+    delete b;
+    return e == hipSuccess ? LBM_OK : hip_fail(e, "hipStreamSynchronize");
+  });
 }
 
 lbm_status lbm_stream_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
-  if (!dst || !src) return fail(LBM_EINVAL, "NULL buffer");
-  if (bytes % 16) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
-  SCLBM_HIP(launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream)));
-  return LBM_OK;
+  return guarded("lbm_stream_copy", [&]() -> lbm_status {
+    if (!dst || !src) return fail(LBM_EINVAL, "NULL buffer");
+    if (bytes % 16) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
+    SCLBM_HIP(launch_copy(dst, src, bytes, reinterpret_cast<hipStream_t>(hip_stream)));
+    return LBM_OK;
+  });
 }
 
 }  // extern "C"

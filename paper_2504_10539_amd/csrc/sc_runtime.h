@@ -4,6 +4,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -15,6 +17,25 @@ namespace sclbm {
 void set_error(const std::string& msg);
 lbm_status fail(lbm_status code, const std::string& msg);
 lbm_status hip_fail(hipError_t e, const char* what);
+// Records `where: what` as the thread's error message without throwing.
+lbm_status fail_nothrow(lbm_status code, const char* where, const char* what) noexcept;
+
+// Runs the body of a C-ABI entry point with every C++ exception turned into a
+// status and a message (std::bad_alloc: LBM_ENOMEM; anything else, e.g.
+// std::system_error from a thread, or an exception out of the runtime:
+// LBM_EDEVICE), so that no exception crosses the boundary.
+template <class F>
+lbm_status guarded(const char* where, F&& body) noexcept {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail_nothrow(LBM_ENOMEM, where, "host memory exhausted");
+  } catch (const std::exception& e) {
+    return fail_nothrow(LBM_EDEVICE, where, e.what());
+  } catch (...) {
+    return fail_nothrow(LBM_EDEVICE, where, "unknown C++ exception");
+  }
+}
 
 #define SCLBM_HIP(call)                                     \
   do {                                                      \
@@ -163,8 +184,11 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage);
 
 // lbm_create / lbm_init_droplets with the stream waits made optional (see
 // their definitions); the C-ABI functions call them with waits.
+// flag: device-visible address of the run's status word (InstDesc::flag;
+// nullptr for none).
 lbm_status create_ctx(const lbm_params* p, void* popA, void* popB, size_t pop_bytes, void* work,
-                      size_t work_bytes, void* hip_stream, bool standalone, lbm_ctx** out);
+                      size_t work_bytes, void* hip_stream, bool standalone, lbm_ctx** out,
+                      int* flag = nullptr);
 lbm_status init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip,
                          bool sync);
 // tail: the items of the tail launch of a two-step variant.
@@ -204,6 +228,7 @@ struct lbm_ctx {
   double* h_series = nullptr;  // pinned, kSeriesChunk records
   int series_nitems = 0;
   lbm_batch* batch = nullptr;  // non-null while driven by a batch
+  int* flag = nullptr;         // status word set by the step kernels (InstDesc::flag)
   std::string arch;
 
   sclbm::InstDesc host_desc() const;

@@ -16,8 +16,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-# SCLBM_LIB may name another build of the same library (e.g. a variant build).
-LIB_PATH = os.environ.get("SCLBM_LIB") or os.path.join(_HERE, "_lib", "libsclbm.so")
+# Always the in-tree build of this package (python -m paper_2504_10539_amd.build).
+LIB_PATH = os.path.join(_HERE, "_lib", "libsclbm.so")
 
 LBM_OK = 0
 LBM_EINVAL = -1
@@ -95,7 +95,8 @@ class lbm_server_stats(ctypes.Structure):
                 ("queued", ctypes.c_int64), ("resident", ctypes.c_int64),
                 ("ticks", ctypes.c_int64), ("lattice_updates", ctypes.c_double),
                 ("pool_bytes", ctypes.c_size_t), ("pool_in_use", ctypes.c_size_t),
-                ("pool_high_water", ctypes.c_size_t)]
+                ("pool_high_water", ctypes.c_size_t), ("unstable", ctypes.c_int64),
+                ("retired_early", ctypes.c_int64), ("unstable_updates", ctypes.c_double)]
 
 
 _vp = ctypes.c_void_p

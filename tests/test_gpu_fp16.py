@@ -78,6 +78,24 @@ def test_config1_fp16_shifted_1000_steps(rho0):
     assert err_range <= 3e-2 and err_cell <= 8e-2
 
 
+@pytest.mark.xfail(strict=True, reason="one global shift cannot fit both phases: in the gas "
+                   "(rho ~ 0.15) the stored f_i - w_i rho0 is of order w_i and its half-precision "
+                   "rounding is ~1e-3 of the local density every step; measured 7.9e-3 (rho0 = 1) "
+                   "and 1.4e-2 (rho0 = 0.5) of rho_max, 2.0e-2 and 3.5e-2 per cell")
+@pytest.mark.parametrize("rho0", [0.5, 1.0])
+def test_config1_fp16_shifted_density_bar(rho0):
+    """The stated FP16 bar: density within 1e-3 in both readings after 1000 steps."""
+    N = 64
+    drops = inputs.single_droplet(N, 16)
+    sim = lbm().Simulation(N, N, -5.0, 1.0, lbm().LBM_F16_SHIFTED, rho0).init_droplets(drops, seed=1)
+    sim.step(1000)
+    rho = to_np(sim.moments()[0])
+    rho_ref = oracle.density(oracle.step(oracle.droplet_state(N, N, drops, seed=1), -5.0, 1.0,
+                                         1000, 8))
+    assert float(np.max(np.abs(rho - rho_ref)) / rho_ref.max()) <= 1e-3
+    assert float(np.max(np.abs(rho - rho_ref) / rho_ref)) <= 1e-3
+
+
 def test_fp16_mixed_with_fp32_in_one_batch_is_bitwise():
     """An FP16 run and an FP32 run in the same batch equal their solo runs."""
     L = lbm()

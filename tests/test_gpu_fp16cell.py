@@ -95,6 +95,21 @@ def test_config1_fp16_cell_1000_steps():
     assert m["W"] == mref["W"]
 
 
+@pytest.mark.xfail(strict=True, reason="the per-cell reading of the FP16 bar is missed by a "
+                   "little: 1.1e-3 per cell (4.1e-4 of rho_max); the half-precision rounding of "
+                   "the moving populations leaves mass and momentum errors that move the droplet")
+def test_config1_fp16_cell_per_cell_density_bar():
+    L = lbm()
+    N = 64
+    drops = inputs.single_droplet(N, 16)
+    sim = L.Simulation(N, N, -5.0, 1.0, L.LBM_F16_CELL).init_droplets(drops, seed=1)
+    sim.step(1000)
+    rho = to_np(sim.moments()[0])
+    rho_ref = oracle.density(oracle.step(oracle.droplet_state(N, N, drops, seed=1), -5.0, 1.0,
+                                         1000, 8))
+    assert float(np.max(np.abs(rho - rho_ref) / rho_ref)) <= 1e-3
+
+
 def test_fp16_cell_tile_shapes_bitwise_identical():
     """Every tile shape, strip and paired, computes bitwise the same state."""
     L = lbm()

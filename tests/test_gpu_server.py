@@ -5,7 +5,10 @@ Requests of uneven sizes and both storage types are admitted while others run
 request run alone on a server, and the plain single-run path's result (a
 different kernel variant) in every finite value and in which cells are not
 finite.  A
-request with unstable parameters is flagged without disturbing the others.
+request with unstable parameters is flagged without disturbing the others, and
+retired as soon as its kernels meet a non-finite or non-positive density: the
+step it stops at depends on when the scheduler reads its status word, so the
+states of unstable requests are not compared, only their status.
 """
 import time
 
@@ -84,8 +87,10 @@ def test_results_equal_alone_and_in_the_mix():
         t, f = _submit(alone, k, r)
         alone.drain()
         assert alone.poll(t)[0] == codes[k]
-        assert np.array_equal(_bits(f.cpu().numpy()), _bits(mixed[k])), k
         alone.close()
+        if codes[k] != L.LBM_OK:
+            continue
+        assert np.array_equal(_bits(f.cpu().numpy()), _bits(mixed[k])), k
         assert _same_across_variants(_solo_plain(k, r), mixed[k]), k
 
 
@@ -107,7 +112,8 @@ def test_unstable_request_is_flagged_and_isolated():
     bad_req = (64, -7.5, 0.52, 400, [(32, 32, 14)], 0)
     bad = _submit(srv, 9, bad_req)
     srv.drain()
-    assert srv.poll(bad[0])[0] == L.LBM_EUNSTABLE
+    code, m = srv.poll(bad[0])
+    assert code == L.LBM_EUNSTABLE and m["step"] < 400  # retired before its last step
     assert srv.poll(good[0])[0] == L.LBM_OK
     assert np.array_equal(to_np(good[1]), _solo_plain(0, REQS[0]))
     srv.close()
@@ -152,6 +158,32 @@ def test_storage_type_joining_a_running_server():
         ta, fa = _submit(alone, k, reqs[k])
         alone.drain()
         assert alone.poll(ta)[0] == code
-        assert np.array_equal(_bits(f.cpu().numpy()), _bits(fa.cpu().numpy())), k
+        if code == L.LBM_OK:
+            assert np.array_equal(_bits(f.cpu().numpy()), _bits(fa.cpu().numpy())), k
         alone.close()
+    srv.close()
+
+
+@pytest.mark.parametrize("policy", ["continuous", "fifo"])
+def test_diverging_request_retires_long_before_a_stable_one(policy):
+    """A request that goes non-finite within a few dozen steps completes long
+    before a stable request of the same length, instead of stepping NaNs to its
+    end; its lattice updates are counted apart from the throughput."""
+    L = lbm()
+    pol = L.LBM_POLICY_CONTINUOUS if policy == "continuous" else L.LBM_POLICY_FIFO
+    srv = L.Server(1 << 30, policy=pol, steps_per_tick=16, max_slots=8)
+    n, steps = 512, 4000
+    bad = srv.submit(n, n, -6.0, 0.55, steps, [(256, 256, 80)], seed=5)
+    good = srv.submit(n, n, -5.0, 1.0, steps, [(256, 256, 80)], seed=6)
+    srv.drain()
+    cb, mb = srv.poll(bad)
+    cg, mg = srv.poll(good)
+    assert cb == L.LBM_EUNSTABLE and mb["finite"] == 0
+    assert cg == L.LBM_OK and mg["step"] == steps
+    assert mb["step"] < 400, mb["step"]
+    assert mb["t_done"] - mb["t_admit"] < 0.25 * (mg["t_done"] - mg["t_admit"])
+    st = srv.stats()
+    assert st["unstable"] == 1 and st["retired_early"] == 1
+    assert st["lattice_updates"] == n * n * steps
+    assert st["unstable_updates"] == n * n * mb["step"]
     srv.close()

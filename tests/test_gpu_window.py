@@ -30,7 +30,9 @@ def _gpu():
     need_gpu()
 
 
-def test_many_droplet_window_error_series(nthreads):
+@pytest.fixture(scope="module")
+def window_series(nthreads):
+    """Worst errors over the series (every 500 steps) of each storage form."""
     L = lbm()
     n, G, tau = 512, -5.5, 1.0
     drops = inputs.many_droplets(4096, 2000, 8, 48, seed=3)
@@ -41,7 +43,8 @@ def test_many_droplet_window_error_series(nthreads):
     for s in sims.values():
         s.init_droplets(drops, seed=3, period=(4096, 4096))
     worst = {"f32_cell": 0.0, "f32_range": 0.0, "f32_metric": 0.0, "f16_metric": 0.0,
-             "f16c_metric": 0.0, "f16c_range": 0.0}
+             "f16_cell": 0.0, "f16_range": 0.0, "f16c_metric": 0.0, "f16c_range": 0.0,
+             "f16c_cell": 0.0}
     for seg in range(1, 11):
         f = oracle.step(f, G, tau, 500, nthreads)
         rr = oracle.density(f)
@@ -62,13 +65,32 @@ def test_many_droplet_window_error_series(nthreads):
                 worst["f32_metric"] = max(worst["f32_metric"], met)
             elif name == "f16":
                 worst["f16_metric"] = max(worst["f16_metric"], met)
+                worst["f16_cell"] = max(worst["f16_cell"], cell)
+                worst["f16_range"] = max(worst["f16_range"], rng)
             else:
                 worst["f16c_metric"] = max(worst["f16c_metric"], met)
                 worst["f16c_range"] = max(worst["f16c_range"], rng)
+                worst["f16c_cell"] = max(worst["f16c_cell"], cell)
         print(" | ".join(line))
-    # regression bounds over the measured series, with margin
+    print("worst", worst)
+    return worst
+
+
+def test_many_droplet_window_error_series(window_series):
+    """Regression bounds over the measured series, with margin."""
+    worst = window_series
     assert worst["f32_cell"] < 2e-4 and worst["f32_range"] < 6e-5, worst
     assert worst["f32_metric"] < 1e-4, worst
     assert worst["f16_metric"] < 0.02, worst
     assert worst["f16c_metric"] < 0.02, worst
-    print("worst", worst)
+    assert worst["f16c_range"] < 2e-2, worst  # measured 1.3e-2 at step 5000
+
+
+@pytest.mark.xfail(strict=True, reason="the FP16 density bar (1e-3) is not met on this chaotic "
+                   "2000-droplet window: FP16-shifted storage lets the droplets drift apart from "
+                   "the FP64 run (order-one per-cell errors from step 2000) and the per-cell shift "
+                   "reaches 1.3e-2 of rho_max by step 5000")
+@pytest.mark.parametrize("form", ["f16", "f16c"])
+def test_many_droplet_window_fp16_density_bar(window_series, form):
+    assert window_series[f"{form}_range"] <= 1e-3
+    assert window_series[f"{form}_cell"] <= 1e-3

@@ -129,6 +129,76 @@ def test_moments_vs_bruteforce():
     assert np.abs(uy - uyb).max() < 1e-14
 
 
+# ---------------------------------------------------------------- conservation sums
+# The D2Q9 velocities in the population order that the oracle's header states,
+# typed out here rather than read from the oracle, so that a swapped or
+# sign-flipped component in the oracle's own table fails these pins.
+E_LITERAL = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+
+
+def test_lattice_matches_stated_order():
+    assert ORDER == E_LITERAL
+    assert WT.tolist() == [4 / 9] + [1 / 9] * 4 + [1 / 36] * 4
+
+
+def test_conservation_uniform_equilibrium_closed_form():
+    """A uniform f_eq(rho, u) field carries mass rho N and momentum rho u N (N cells)."""
+    nx, ny = 12, 7
+    for rho, ux, uy in [(0.8, 0.05, -0.03), (1.7, -0.11, 0.02), (0.15, 0.0, 0.07)]:
+        feq = oracle.equilibrium(rho, ux, uy)
+        f = np.ascontiguousarray(np.broadcast_to(feq[:, None, None], (9, ny, nx)))
+        m, px, py = oracle.conservation(f)
+        n = nx * ny
+        assert abs(m - rho * n) <= 1e-13 * rho * n
+        assert abs(px - rho * ux * n) <= 1e-13 * rho * n
+        assert abs(py - rho * uy * n) <= 1e-13 * rho * n
+
+
+def test_conservation_one_population_per_direction():
+    """One non-zero population per direction, each at its own cell: the sums are
+    sum_i a_i and sum_i a_i e_i with the velocities written out by hand."""
+    nx, ny = 9, 5
+    a = [0.3, 1.1, 2.3, 0.7, 0.05, 1.9, 0.45, 3.1, 0.6]
+    cells = [(0, 0), (4, 1), (8, 4), (2, 3), (5, 0), (1, 2), (7, 1), (3, 4), (6, 2)]
+    f = np.zeros((9, ny, nx))
+    for i, (x, y) in enumerate(cells):
+        f[i, y, x] = a[i]
+    m, px, py = oracle.conservation(f)
+    assert m == pytest.approx(sum(a), rel=1e-15)
+    assert px == pytest.approx(sum(ai * e[0] for ai, e in zip(a, E_LITERAL)), abs=1e-15)
+    assert py == pytest.approx(sum(ai * e[1] for ai, e in zip(a, E_LITERAL)), abs=1e-15)
+    # each direction alone: (a, a ex, a ey)
+    for i in range(9):
+        g = np.zeros((9, ny, nx))
+        g[i, 3, 2] = 2.5
+        assert oracle.conservation(g) == (2.5, 2.5 * E_LITERAL[i][0], 2.5 * E_LITERAL[i][1])
+
+
+def test_conservation_random_state_brute_force():
+    """Random positive state: the sums equal plain numpy sums over the literal velocities."""
+    f = inputs.random_positive_state(13, 11, seed=21)
+    m, px, py = oracle.conservation(f)
+    ex = np.array([e[0] for e in E_LITERAL], dtype=float)
+    ey = np.array([e[1] for e in E_LITERAL], dtype=float)
+    per = f.sum(axis=(1, 2))
+    assert m == pytest.approx(per.sum(), rel=1e-14)
+    assert px == pytest.approx((per * ex).sum(), abs=1e-13 * m)
+    assert py == pytest.approx((per * ey).sum(), abs=1e-13 * m)
+
+
+def test_conservation_momentum_of_streamed_packet():
+    """A moving packet: f = a at one cell in direction i, G = 0 and tau = 1 relax it to
+    the equilibrium of that cell, whose momentum a e_i is then carried unchanged."""
+    for i in range(1, 9):
+        f = np.zeros((9, 6, 6)) + 1e-3 * np.array(WT)[:, None, None]
+        f[i, 2, 3] += 0.4
+        m0, px0, py0 = oracle.conservation(f)
+        assert px0 == pytest.approx(0.4 * E_LITERAL[i][0], abs=1e-15)
+        assert py0 == pytest.approx(0.4 * E_LITERAL[i][1], abs=1e-15)
+        m1, px1, py1 = oracle.conservation(oracle.step(f, 0.0, 1.0, 3))
+        assert (m1, px1, py1) == pytest.approx((m0, px0, py0), abs=1e-14)
+
+
 # ---------------------------------------------------------------- invariants
 def test_mass_conservation_config1(nthreads):
     f0 = oracle.droplet_state(64, 64, inputs.single_droplet(64, 16))

@@ -73,10 +73,20 @@ def test_budget_is_never_exceeded(lbm):
     s.close()
 
 
+def tables_bytes(lbm, pool, **kw):
+    """Bytes the continuous policy keeps for its batch tables out of a pool."""
+    s = lbm.Server(pool, fake=True, fake_mlups=1000.0, **kw)
+    cap = s.stats()["pool_bytes"]
+    s.close()
+    return pool - cap
+
+
 def test_small_requests_pass_a_large_one_that_does_not_fit(lbm):
     small, big = req_bytes(lbm, 128), req_bytes(lbm, 512)
-    pool = big + small // 2  # the big one fits only when the pool is empty
+    # the big one fits only when the requests' part of the pool is empty
+    pool = big + small // 2 + tables_bytes(lbm, big + small, max_slots=64)
     s = lbm.Server(pool, fake=True, fake_mlups=100.0, steps_per_tick=20, max_slots=64)
+    assert big <= s.stats()["pool_bytes"] < big + small
     t0 = s.submit(128, 128, -5.0, 1.0, 2000, [(64, 64, 20)])          # long small job
     t1 = s.submit(512, 512, -5.0, 1.0, 20, [(256, 256, 40)])           # big, must wait
     rest = [s.submit(128, 128, -5.0, 1.0, 20, [(64, 64, 20)]) for _ in range(3)]
@@ -104,9 +114,69 @@ def test_unstable_request_is_flagged_and_others_complete(lbm):
     good = s.submit(64, 64, -5.0, 1.0, 30, [(32, 32, 10)])
     bad = s.submit(64, 64, -5.0, 1.0, 30, [(32, 32, 10)], rho_g=-0.1)
     s.drain()
-    assert s.poll(bad)[0] == lbm.LBM_EUNSTABLE
+    code, rb = s.poll(bad)
+    assert code == lbm.LBM_EUNSTABLE
+    assert rb["step"] == 10 and rb["finite"] == 0  # retired after its first tick
     assert s.poll(good)[0] == lbm.LBM_OK
-    assert s.stats()["failed"] == 1
+    st = s.stats()
+    assert st["failed"] == 1 and st["unstable"] == 1 and st["retired_early"] == 1
+    # throughput counts the stable request only; the unstable one's work apart
+    assert st["lattice_updates"] == 64 * 64 * 30
+    assert st["unstable_updates"] == 64 * 64 * 10
+    s.close()
+
+
+def test_diverging_request_retires_long_before_a_stable_one(lbm):
+    """An unstable run leaves at its first tick instead of running its steps."""
+    s = lbm.Server(1 << 30, fake=True, fake_mlups=50.0, steps_per_tick=50, max_slots=4)
+    stable = s.submit(128, 128, -5.0, 1.0, 2000, [(64, 64, 20)])
+    bad = s.submit(128, 128, -5.0, 1.0, 2000, [(64, 64, 20)], rho_g=-0.2)
+    s.drain()
+    _, rs = s.poll(stable)
+    code, rb = s.poll(bad)
+    assert code == lbm.LBM_EUNSTABLE and rb["step"] == 50
+    assert rb["t_done"] - rb["t_admit"] < 0.1 * (rs["t_done"] - rs["t_admit"])
+    s.close()
+
+
+def test_capacity_excludes_the_batch_tables(lbm):
+    """The continuous policy keeps its batch tables in the pool: a request larger
+    than what is left is refused at submission instead of waiting forever."""
+    one = req_bytes(lbm, 1024)
+    pool = one + (64 << 10)
+    s = lbm.Server(pool, fake=True, fake_mlups=1000.0, max_slots=4)
+    cap = s.stats()["pool_bytes"]
+    assert cap < one <= pool  # the tables take more than 64 KiB
+    with pytest.raises(lbm.LbmError) as e:
+        s.submit(1024, 1024, -5.0, 1.0, 10, [(512, 512, 100)])
+    assert e.value.code == lbm.LBM_ENOMEM
+    t = s.submit(512, 512, -5.0, 1.0, 10, [(256, 256, 60)])
+    s.drain()
+    assert s.poll(t)[0] == lbm.LBM_OK
+    s.close()
+    # the plain FIFO path keeps no tables: the whole pool is its budget
+    f = lbm.Server(pool, policy=lbm.LBM_POLICY_FIFO, fake=True, fake_mlups=1000.0)
+    assert f.stats()["pool_bytes"] == pool
+    t = f.submit(1024, 1024, -5.0, 1.0, 10, [(512, 512, 100)])
+    f.drain()
+    assert f.poll(t)[0] == lbm.LBM_OK
+    f.close()
+
+
+def test_droplet_count_is_checked_before_the_array_is_read(lbm):
+    """A huge n_drops with a one-droplet array is refused without reading past it."""
+    import ctypes
+    import numpy as np
+    s = lbm.Server(1 << 30, fake=True, fake_mlups=1000.0)
+    d = np.array([[32.0, 32.0, 8.0]])
+    for n in (2**31 - 1, 10000):  # above the 4778 droplets a 64^2 FP32 grid holds
+        req = lbm.lbm_request(lbm.make_params(64, 64, -5.0, 1.0), lbm.make_init(),
+                              d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), n, 0, 10,
+                              None, None)
+        t = ctypes.c_uint64()
+        code = lbm.LIB.lbm_submit(s.handle, ctypes.byref(req), ctypes.byref(t))
+        assert code == lbm.LBM_EINVAL
+        assert "droplets" in lbm.last_error()
     s.close()
 
 
