@@ -184,6 +184,21 @@ lbm_status lbm_moments(lbm_ctx* ctx, float* rho, float* ux, float* uy);
  * fills the host struct.  Uses the idle population buffer as scratch. */
 lbm_status lbm_interface_metrics(lbm_ctx* ctx, lbm_metrics* out);
 
+/* For callers that cannot allocate (code under HIP graph capture, serving
+ * loops that must not allocate, harnesses that forbid it): the metrics of
+ * lbm_interface_metrics, computed by the same kernels, written as one
+ * lbm_metrics record to `out`, caller device memory (8-byte aligned), without
+ * waiting for the stream.  Nothing is allocated: the FP64 density goes into the
+ * idle population buffer, as in lbm_interface_metrics, and the reduction
+ * partials into a static device array of 2048 partial records (264 KiB per
+ * GPU the library runs on, held until the process ends) instead of the
+ * run's workspace; the pass never needs more than 2048 records (LBM_ENOMEM
+ * if it ever would).  The array is shared by every call on one GPU: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * ordered by the caller.  The record equals what lbm_interface_metrics
+ * reports for the same state.  Asynchronous. */
+lbm_status lbm_interface_metrics_noalloc(lbm_ctx* ctx, lbm_metrics* out);
+
 /* Copies the current state out as 9 planes of nx * ny FP32 pre-collision
  * populations f_i(x, t) into a caller device buffer (FP16 storage is widened
  * exactly as the step kernel reads it).  With lbm_set_state it forks runs

@@ -114,6 +114,7 @@ _PROTOS = {
     "lbm_step_series": (_i32, [_vp, _i64, _i32, _P(lbm_metrics), _i32, _P(_i32)]),
     "lbm_moments": (_i32, [_vp, _vp, _vp, _vp]),
     "lbm_interface_metrics": (_i32, [_vp, _P(lbm_metrics)]),
+    "lbm_interface_metrics_noalloc": (_i32, [_vp, _vp]),
     "lbm_get_state": (_i32, [_vp, _vp]),
     "lbm_set_state": (_i32, [_vp, _vp]),
     "lbm_step_count": (_i64, [_vp]),
