@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_F32 = 72   # 9 populations read + 9 written, 4 bytes each
 BYTES_F16 = 36
 BYTES_F16_CELL = 40  # 18 B read + 18 B written, plus the 2-byte reference density each way
+BYTES_F16_MOMENT = 48  # 24 B record read + 24 B written (rho, jx, jy in FP32; six FP16 values)
 
 
 def log(msg: str):
@@ -62,7 +63,8 @@ def traffic_from_profiles(lbm, kernel_hash: str, storage: str, n: int, tile: int
     except (OSError, ValueError):
         return None
     t = lbm.tiles()[tile]
-    code = {"f32": lbm.LBM_F32, "f16_shifted": lbm.LBM_F16_SHIFTED, "f16_cell": lbm.LBM_F16_CELL}[storage]
+    code = {"f32": lbm.LBM_F32, "f16_shifted": lbm.LBM_F16_SHIFTED, "f16_cell": lbm.LBM_F16_CELL,
+            "f16_moment": lbm.LBM_F16_MOMENT}[storage]
     rows = lbm.tile_layout(n, n, tile, code)[0]  # the band height this grid uses
     key = (storage, n, kernel_name(lbm, tile, code), t["width"], rows)
     for e in d.get("entries", []):
@@ -74,7 +76,8 @@ def traffic_from_profiles(lbm, kernel_hash: str, storage: str, n: int, tile: int
 def kernel_name(lbm, tile: int, storage: int) -> str:
     """Name of the step kernel instance that tile shape `tile` launches."""
     t = lbm.tiles()[tile]
-    st = {lbm.LBM_F32: "StoreF32", lbm.LBM_F16_SHIFTED: "StoreF16S", lbm.LBM_F16_CELL: "StoreF16C"}[storage]
+    st = {lbm.LBM_F32: "StoreF32", lbm.LBM_F16_SHIFTED: "StoreF16S", lbm.LBM_F16_CELL: "StoreF16C",
+          lbm.LBM_F16_MOMENT: "StoreF16M"}[storage]
     if t["steps"] == 2:
         return f"k_step2<{st}, {t['threads']}, {t['prefetch']}, {t['width']}>"
     if t["paired"]:
@@ -99,7 +102,7 @@ def run_main(args, torch, lbm, inputs):
     stream = torch.cuda.current_stream()
     out = {}
     for storage, name in ((lbm.LBM_F32, "f32"), (lbm.LBM_F16_SHIFTED, "f16_shifted"),
-                          (lbm.LBM_F16_CELL, "f16_cell")):
+                          (lbm.LBM_F16_CELL, "f16_cell"), (lbm.LBM_F16_MOMENT, "f16_moment")):
         if storage != lbm.LBM_F32 and args.no_fp16:
             continue
         rho0 = 1.0 if storage == lbm.LBM_F16_SHIFTED else 0.0
@@ -140,7 +143,7 @@ def run_main(args, torch, lbm, inputs):
         lu = float(N) * N * args.lbm_steps * args.steps
         per_step_ms = sum(step_ms) / (args.lbm_steps * args.steps)
         bpu = {lbm.LBM_F32: BYTES_F32, lbm.LBM_F16_SHIFTED: BYTES_F16,
-               lbm.LBM_F16_CELL: BYTES_F16_CELL}[storage]
+               lbm.LBM_F16_CELL: BYTES_F16_CELL, lbm.LBM_F16_MOMENT: BYTES_F16_MOMENT}[storage]
         lf = launch_figures(lbm, sim.tile, per_step_ms, bpu, N * N)
         out[name] = {
             "mlups": lu / wall / 1e6,
@@ -412,7 +415,8 @@ def run_serving(args, torch, lbm, inputs):
         # Throughput counts the lattice updates of requests that completed
         # LBM_OK; unstable requests are retired early and their work is listed
         # apart.
-        res[name] = {"requests": len(trace), "storage": ["f32", "f16_shifted", "f16_cell"][args.serve_storage],
+        res[name] = {"requests": len(trace),
+                     "storage": ["f32", "f16_shifted", "f16_cell", "f16_moment"][args.serve_storage],
                      "aggregate_mlups": st["lattice_updates"] / makespan / 1e6,
                      "p50_ms": pct(lat, 0.5), "p99_ms": pct(lat, 0.99),
                      "ok_p50_ms": pct(lat_ok, 0.5), "ok_p99_ms": pct(lat_ok, 0.99),
@@ -505,8 +509,9 @@ def main():
     ap.add_argument("--serve-smax", type=int, default=20000)
     ap.add_argument("--serve-pool-gb", type=int, default=32)
     ap.add_argument("--serve-policy", choices=["both", "continuous", "fifo"], default="both")
-    ap.add_argument("--serve-storage", type=int, default=0, choices=[0, 1, 2],
-                    help="storage form of every request (0 FP32, 1 FP16-shifted, 2 FP16 per cell)")
+    ap.add_argument("--serve-storage", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="storage form of every request (0 FP32, 1 FP16-shifted, 2 FP16 per cell, "
+                         "3 FP16 with exact moments)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -567,7 +572,7 @@ def main():
                      "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
         "f32": f32,
     }
-    for key in ("f16_shifted", "f16_cell"):
+    for key in ("f16_shifted", "f16_cell", "f16_moment"):
         if key in main_res:
             r = main_res[key]
             line[key] = dict(r, roofline_frac=round(r["achieved_gbs"] / HBM_PEAK_GBS, 4),

@@ -65,6 +65,18 @@ typedef int32_t lbm_status;
                               tenth FP16 plane; read back as rhohat w_i + h_i
                               rounded once.  20 bytes per cell per buffer, 40
                               bytes moved per lattice update */
+#define LBM_F16_MOMENT 3   /* FP16 with exact conserved moments: a cell x stores
+                              the record of the nine values A_i(x) it wrote -
+                              its density rho (the record's mass) and the
+                              momentum jx, jy of the A_i in FP32, and A_3 .. A_8
+                              as h_i = half(A_i - w_i rho) (RNE) - read back as
+                              A_i = rho w_i + h_i (i >= 3), A_1 and A_2 from the
+                              momentum, A_0 = rho - (the other eight).  Mass and
+                              momentum pass between cells at FP32 rounding;
+                              only non-conserved moments round to half
+                              precision.  24 bytes per cell per buffer, 48
+                              bytes moved per lattice update.  Strip tile
+                              shapes only (steps = 1, paired = 0) */
 
 typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;
@@ -75,7 +87,7 @@ typedef struct lbm_params {
   int32_t nx, ny;   /* grid size, periodic in x and y; 1 <= nx, ny <= 65536 */
   double G;         /* interaction strength (negative for attraction), finite */
   double tau;       /* BGK relaxation time, tau > 0.5 */
-  int32_t storage;  /* LBM_F32, LBM_F16_SHIFTED or LBM_F16_CELL */
+  int32_t storage;  /* LBM_F32, LBM_F16_SHIFTED, LBM_F16_CELL or LBM_F16_MOMENT */
   double rho0;      /* LBM_F16_SHIFTED's shift density (finite, >= 0); ignored otherwise */
 } lbm_params;
 
@@ -121,7 +133,7 @@ typedef struct lbm_metrics {
 
 /* Sizes the caller must allocate for one run: `pop_bytes` for EACH of the two
  * population buffers (9 * nx * ny * 4 for LBM_F32, * 2 for LBM_F16_SHIFTED,
- * 10 * nx * ny * 2 for LBM_F16_CELL),
+ * 10 * nx * ny * 2 for LBM_F16_CELL, 24 * nx * ny for LBM_F16_MOMENT),
  * and `work_bytes` of device workspace (tile tables and reduction partials).
  * Either output pointer may be NULL.  LBM_EINVAL for invalid parameters. */
 lbm_status lbm_buffer_bytes(const lbm_params* p, size_t* pop_bytes, size_t* work_bytes);
@@ -230,8 +242,9 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * `threads` is marched as one periodic strip with no halo columns.  rows = 0:
  * balanced bands, whose height is chosen per grid so that a launch is about
  * two rounds of the workgroups the device holds at once (lbm_tile_layout
- * gives it).  Every shape computes bitwise the same
- * result; only speed differs.  Any output pointer may be NULL; k out of range
+ * gives it).  LBM_F16_MOMENT runs strip shapes (steps = 1, paired = 0) only:
+ * lbm_set_tile refuses the others for it with LBM_EINVAL.  Every valid shape
+ * computes bitwise the same result; only speed differs.  Any output pointer may be NULL; k out of range
  * is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,

@@ -112,6 +112,7 @@ struct StoreF32 {
   static constexpr int kBytes = 4;
   static constexpr bool kStream = true;
   static constexpr bool kCellShift = false;
+  static constexpr bool kMoment = false;
   template <class P>
   __device__ static __forceinline__ float load(P p, float /*shift*/) { return *p; }
   __device__ static __forceinline__ T pack(float v, float /*shift*/) { return v; }
@@ -123,6 +124,7 @@ struct StoreF16S {
   static constexpr int kBytes = 2;
   static constexpr bool kStream = false;
   static constexpr bool kCellShift = false;
+  static constexpr bool kMoment = false;
   template <class P>
   __device__ static __forceinline__ float load(P p, float shift) {
     return static_cast<float>(*p) + shift;
@@ -142,6 +144,7 @@ struct StoreF16C {
   static constexpr int kBytes = 2;
   static constexpr bool kStream = false;
   static constexpr bool kCellShift = true;
+  static constexpr bool kMoment = false;
   __device__ static __forceinline__ float decode(T h, T rh, float w) {
     return __builtin_fmaf(static_cast<float>(rh), w, static_cast<float>(h));
   }
@@ -150,6 +153,36 @@ struct StoreF16C {
   }
   __device__ static __forceinline__ T ref(float rho) { return static_cast<T>(rho); }
 };
+
+// FP16 populations with exact conserved moments.  A cell x keeps a record of
+// the nine values A_i(x) it wrote: its density rho (the mass of the record)
+// and the momentum jx, jy of the A_i in FP32, and A_3 .. A_8 as
+// h_i = half(A_i - w_i rho) (round to nearest even).  A_1 and A_2 are rebuilt
+// from the momentum and A_0 from the mass (mom_decode), so the mass and
+// momentum a cell hands on to its neighbours are exact up to FP32 rounding and
+// only non-conserved moments round to half precision; the BGK collision
+// relaxes those towards equilibrium instead of carrying the rounding on.
+// 24 bytes per cell (layout: mom_row).
+struct StoreF16M {
+  using T = _Float16;  // the six FP16 rows
+  static constexpr int kBytes = 2;
+  static constexpr bool kStream = false;
+  static constexpr bool kCellShift = false;
+  static constexpr bool kMoment = true;
+};
+
+// Moment-storage layout: lattice row y occupies 24 nx bytes from byte
+// 24 nx y: the FP32 rows of rho, jx and jy (mom_f32, k = 0, 1, 2), then the
+// FP16 rows of h_3 .. h_8 (mom_f16, i = 3 .. 8); x is fastest in every row.
+__host__ __device__ __forceinline__ uint64_t mom_row(int y, int nx) {
+  return 24ull * (uint64_t)nx * (uint64_t)y;
+}
+__host__ __device__ __forceinline__ uint64_t mom_f32(int k, int nx) {
+  return 4ull * (uint64_t)nx * (uint64_t)k;
+}
+__host__ __device__ __forceinline__ uint64_t mom_f16(int i, int nx) {
+  return 12ull * (uint64_t)nx + 2ull * (uint64_t)nx * (uint64_t)(i - 3);
+}
 
 // Pointer into global memory (address space 1): loads and stores through it
 // use the global_* instructions with a scalar base and a 32-bit lane offset.
@@ -200,6 +233,60 @@ __device__ __forceinline__ void momentum(const float f[9], float& jx, float& jy)
   const float b = f[8] - f[6];
   jx = (f[1] - f[3]) + (a + b);
   jy = (f[2] - f[4]) + (a - b);
+}
+
+// Moment storage (StoreF16M): A_i = rho w_i + h_i for i = 3 .. 8, rounded once.
+__device__ __forceinline__ float mom_pop(float rho, _Float16 h, float w) {
+  return __builtin_fmaf(rho, w, static_cast<float>(h));
+}
+// A_1 of a record from its rho, jx and h_3, h_5 .. h_8: jx = A_1 - A_3 +
+// (A_5 - A_7) + (A_8 - A_6), solved for A_1 in that grouping.
+__device__ __forceinline__ float mom_a1(float rho, float jx, _Float16 h3, _Float16 h5, _Float16 h6,
+                                        _Float16 h7, _Float16 h8) {
+  const float a3 = mom_pop(rho, h3, kW1);
+  const float d = mom_pop(rho, h5, kW2) - mom_pop(rho, h7, kW2);
+  const float e = mom_pop(rho, h8, kW2) - mom_pop(rho, h6, kW2);
+  return (jx + a3) - (d + e);
+}
+// A_2 from rho, jy and h_4 .. h_8: jy = A_2 - A_4 + (A_5 - A_7) - (A_8 - A_6).
+__device__ __forceinline__ float mom_a2(float rho, float jy, _Float16 h4, _Float16 h5, _Float16 h6,
+                                        _Float16 h7, _Float16 h8) {
+  const float a4 = mom_pop(rho, h4, kW1);
+  const float d = mom_pop(rho, h5, kW2) - mom_pop(rho, h7, kW2);
+  const float e = mom_pop(rho, h8, kW2) - mom_pop(rho, h6, kW2);
+  return (jy + a4) - (d - e);
+}
+// A_0 from the record's mass: rho minus the other eight values, summed in the
+// grouping of the collision's mass balance.
+__device__ __forceinline__ float mom_a0(float rho, const float (&a)[9]) {
+  return rho - (((a[1] + a[3]) + (a[2] + a[4])) + ((a[5] + a[7]) + (a[6] + a[8])));
+}
+// All nine values of a record (bitwise the values mom_a1, mom_a2 and mom_pop
+// give one at a time).
+__device__ __forceinline__ void mom_decode(float rho, float jx, float jy, const _Float16 (&h)[6],
+                                           float (&a)[9]) {
+  a[3] = mom_pop(rho, h[0], kW1);
+  a[4] = mom_pop(rho, h[1], kW1);
+  a[5] = mom_pop(rho, h[2], kW2);
+  a[6] = mom_pop(rho, h[3], kW2);
+  a[7] = mom_pop(rho, h[4], kW2);
+  a[8] = mom_pop(rho, h[5], kW2);
+  const float d = a[5] - a[7], e = a[8] - a[6];
+  a[1] = (jx + a[3]) - (d + e);
+  a[2] = (jy + a[4]) - (d - e);
+  a[0] = mom_a0(rho, a);
+}
+// The record of the values v written by a cell whose mass is rho (the
+// density it collided with, which the BGK collision conserves).
+__device__ __forceinline__ void mom_encode(const float* v, float rho, float& jx, float& jy,
+                                           _Float16 (&h)[6]) {
+  momentum(v, jx, jy);
+  h[0] = static_cast<_Float16>(__builtin_fmaf(-kW1, rho, v[3]));
+  h[1] = static_cast<_Float16>(__builtin_fmaf(-kW1, rho, v[4]));
+  h[2] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[5]));
+  h[3] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[6]));
+  h[4] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[7]));
+  h[5] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[8]));
 }
 
 // 1 / x from the hardware reciprocal (within 1 ulp) and one FMA correction

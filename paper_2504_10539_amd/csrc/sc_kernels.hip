@@ -189,43 +189,101 @@ struct Strip {
     return y < 0 ? y + ny : (y >= ny ? y - ny : y);
   }
 
+  // Moment storage: uniform row addresses of the FP32 row k and the FP16 row of
+  // population i of the lattice row that starts at byte address `row`.
+  __device__ __forceinline__ gptr<const float> mom_in32(uint64_t row, int k) const {
+    return as_global<const float>(uniform(row + mom_f32(k, nx)));
+  }
+  __device__ __forceinline__ gptr<const T> mom_in16(uint64_t row, int i) const {
+    return as_global<const T>(uniform(row + mom_f16(i, nx)));
+  }
+  template <class U>
+  __device__ __forceinline__ static U ldb(gptr<const U> base, uint32_t boff) {
+    return *reinterpret_cast<gptr<const U>>(reinterpret_cast<gptr<const char>>(base) + boff);
+  }
+  template <class U>
+  __device__ __forceinline__ static void stb(gptr<U> base, uint32_t boff, U v) {
+    *reinterpret_cast<gptr<U>>(reinterpret_cast<gptr<char>>(base) + boff) = v;
+  }
+
+  // Moment storage: the pulled populations of row y for every live slot.
+  // f_0 is the cell's own record decoded whole; f_1 and f_2 are rebuilt from
+  // the momentum of the records at x - e_1 and x - e_2; the others are one
+  // value each of the records they come from.
+  __device__ __forceinline__ void pull_moments(int y, int ym, int yp,
+                                               float (&f)[CPT + 1][10]) const {
+    const uint64_t b0 = src + mom_row(y, nx), bm = src + mom_row(ym, nx), bp = src + mom_row(yp, nx);
+    const gptr<const float> r0 = mom_in32(b0, 0), jx0 = mom_in32(b0, 1), jy0 = mom_in32(b0, 2),
+                            rm = mom_in32(bm, 0), jym = mom_in32(bm, 2), rp = mom_in32(bp, 0);
+#pragma unroll
+    for (int k = 0; k <= CPT; ++k) {
+      if (!live[k]) continue;
+      const uint32_t c4 = fresh((uint32_t)xc[k] * 4u), m4 = fresh((uint32_t)xm[k] * 4u),
+                     p4 = fresh((uint32_t)xp[k] * 4u);
+      const uint32_t c2 = fresh((uint32_t)xc[k] * 2u), m2 = fresh((uint32_t)xm[k] * 2u),
+                     p2 = fresh((uint32_t)xp[k] * 2u);
+      T h[6];
+#pragma unroll
+      for (int i = 3; i < 9; ++i) h[i - 3] = ldb(mom_in16(b0, i), c2);
+      float own[9];
+      mom_decode(ldb(r0, c4), ldb(jx0, c4), ldb(jy0, c4), h, own);
+      f[k][0] = own[0];
+      f[k][1] = mom_a1(ldb(r0, m4), ldb(jx0, m4), ldb(mom_in16(b0, 3), m2),
+                       ldb(mom_in16(b0, 5), m2), ldb(mom_in16(b0, 6), m2),
+                       ldb(mom_in16(b0, 7), m2), ldb(mom_in16(b0, 8), m2));
+      f[k][2] = mom_a2(ldb(rm, c4), ldb(jym, c4), ldb(mom_in16(bm, 4), c2),
+                       ldb(mom_in16(bm, 5), c2), ldb(mom_in16(bm, 6), c2),
+                       ldb(mom_in16(bm, 7), c2), ldb(mom_in16(bm, 8), c2));
+      f[k][3] = mom_pop(ldb(r0, p4), ldb(mom_in16(b0, 3), p2), kW1);
+      f[k][4] = mom_pop(ldb(rp, c4), ldb(mom_in16(bp, 4), c2), kW1);
+      f[k][5] = mom_pop(ldb(rm, m4), ldb(mom_in16(bm, 5), m2), kW2);
+      f[k][6] = mom_pop(ldb(rm, p4), ldb(mom_in16(bm, 6), p2), kW2);
+      f[k][7] = mom_pop(ldb(rp, p4), ldb(mom_in16(bp, 7), p2), kW2);
+      f[k][8] = mom_pop(ldb(rp, m4), ldb(mom_in16(bp, 8), m2), kW2);
+    }
+  }
+
   // Pre-collision populations of the row at march position j for every live
   // slot: f_i(x, y) = A_i(x - e_i), so population i is read from row y - e_iy.
   __device__ __forceinline__ void pull(int j, float (&f)[CPT + 1][10]) const {
     const int y = row_of(j);
     const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-    const gptr<const T> p0 = in_row(0, y), p1 = in_row(1, y), p2 = in_row(2, ym),
-                        p3 = in_row(3, y), p4 = in_row(4, yp), p5 = in_row(5, ym),
-                        p6 = in_row(6, ym), p7 = in_row(7, yp), p8 = in_row(8, yp);
-    constexpr uint32_t B = sizeof(T);
+    if constexpr (S::kMoment) {
+      pull_moments(y, ym, yp, f);
+    } else {
+      const gptr<const T> p0 = in_row(0, y), p1 = in_row(1, y), p2 = in_row(2, ym),
+                          p3 = in_row(3, y), p4 = in_row(4, yp), p5 = in_row(5, ym),
+                          p6 = in_row(6, ym), p7 = in_row(7, yp), p8 = in_row(8, yp);
+      constexpr uint32_t B = sizeof(T);
 #pragma unroll
-    for (int k = 0; k <= CPT; ++k) {
-      if (live[k]) {
-        const uint32_t c = fresh((uint32_t)xc[k] * B), m = fresh((uint32_t)xm[k] * B),
-                       p = fresh((uint32_t)xp[k] * B);
-        if constexpr (S::kCellShift) {
-          // each value is decoded with the reference density of the cell it
-          // was read from (same row and column in the reference plane)
-          const gptr<const T> q0 = rhat_in(y), qm = rhat_in(ym), qp = rhat_in(yp);
-          f[k][0] = S::decode(*at(p0, c), *at(q0, c), kW0);
-          f[k][1] = S::decode(*at(p1, m), *at(q0, m), kW1);
-          f[k][2] = S::decode(*at(p2, c), *at(qm, c), kW1);
-          f[k][3] = S::decode(*at(p3, p), *at(q0, p), kW1);
-          f[k][4] = S::decode(*at(p4, c), *at(qp, c), kW1);
-          f[k][5] = S::decode(*at(p5, m), *at(qm, m), kW2);
-          f[k][6] = S::decode(*at(p6, p), *at(qm, p), kW2);
-          f[k][7] = S::decode(*at(p7, p), *at(qp, p), kW2);
-          f[k][8] = S::decode(*at(p8, m), *at(qp, m), kW2);
-        } else {
-          f[k][0] = S::load(at(p0, c), sh[0]);
-          f[k][1] = S::load(at(p1, m), sh[1]);
-          f[k][2] = S::load(at(p2, c), sh[2]);
-          f[k][3] = S::load(at(p3, p), sh[3]);
-          f[k][4] = S::load(at(p4, c), sh[4]);
-          f[k][5] = S::load(at(p5, m), sh[5]);
-          f[k][6] = S::load(at(p6, p), sh[6]);
-          f[k][7] = S::load(at(p7, p), sh[7]);
-          f[k][8] = S::load(at(p8, m), sh[8]);
+      for (int k = 0; k <= CPT; ++k) {
+        if (live[k]) {
+          const uint32_t c = fresh((uint32_t)xc[k] * B), m = fresh((uint32_t)xm[k] * B),
+                         p = fresh((uint32_t)xp[k] * B);
+          if constexpr (S::kCellShift) {
+            // each value is decoded with the reference density of the cell it
+            // was read from (same row and column in the reference plane)
+            const gptr<const T> q0 = rhat_in(y), qm = rhat_in(ym), qp = rhat_in(yp);
+            f[k][0] = S::decode(*at(p0, c), *at(q0, c), kW0);
+            f[k][1] = S::decode(*at(p1, m), *at(q0, m), kW1);
+            f[k][2] = S::decode(*at(p2, c), *at(qm, c), kW1);
+            f[k][3] = S::decode(*at(p3, p), *at(q0, p), kW1);
+            f[k][4] = S::decode(*at(p4, c), *at(qp, c), kW1);
+            f[k][5] = S::decode(*at(p5, m), *at(qm, m), kW2);
+            f[k][6] = S::decode(*at(p6, p), *at(qm, p), kW2);
+            f[k][7] = S::decode(*at(p7, p), *at(qp, p), kW2);
+            f[k][8] = S::decode(*at(p8, m), *at(qp, m), kW2);
+          } else {
+            f[k][0] = S::load(at(p0, c), sh[0]);
+            f[k][1] = S::load(at(p1, m), sh[1]);
+            f[k][2] = S::load(at(p2, c), sh[2]);
+            f[k][3] = S::load(at(p3, p), sh[3]);
+            f[k][4] = S::load(at(p4, c), sh[4]);
+            f[k][5] = S::load(at(p5, m), sh[5]);
+            f[k][6] = S::load(at(p6, p), sh[6]);
+            f[k][7] = S::load(at(p7, p), sh[7]);
+            f[k][8] = S::load(at(p8, m), sh[8]);
+          }
         }
       }
     }
@@ -292,7 +350,20 @@ struct Strip {
       bad |= unstable_lanes(f[k][9], true);
       collide(f[k], f[k][9], Fx, Fy, tau, omega);
       const uint32_t xb = fresh((uint32_t)xc[k] * (uint32_t)sizeof(T));
-      if constexpr (S::kCellShift) {
+      if constexpr (S::kMoment) {
+        // the record: this cell's density (its mass), the momentum of the
+        // collided values and the six FP16 deviations
+        float jx, jy;
+        T hv[6];
+        mom_encode(f[k], f[k][9], jx, jy, hv);
+        const uint64_t b = dst + mom_row(y, nx);
+        const uint32_t x4 = fresh((uint32_t)xc[k] * 4u);
+        stb(as_global<float>(uniform(b + mom_f32(0, nx))), x4, f[k][9]);
+        stb(as_global<float>(uniform(b + mom_f32(1, nx))), x4, jx);
+        stb(as_global<float>(uniform(b + mom_f32(2, nx))), x4, jy);
+#pragma unroll
+        for (int i = 3; i < 9; ++i) stb(as_global<T>(uniform(b + mom_f16(i, nx))), xb, hv[i - 3]);
+      } else if constexpr (S::kCellShift) {
         const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
         const T rh = S::ref(f[k][9]);  // this cell's reference: half(rho)
 #pragma unroll
@@ -1277,16 +1348,42 @@ __device__ __forceinline__ void pull_cell(const typename S::T* src, size_t n, in
   (void)n;
   const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
   const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-  const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
-  const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+  if constexpr (S::kMoment) {
+    const char* b = reinterpret_cast<const char*>(src);
+    auto F = [&](int k, int xx, int yy) {
+      return *reinterpret_cast<const float*>(b + mom_row(yy, nx) + mom_f32(k, nx) + 4ull * xx);
+    };
+    auto H = [&](int i, int xx, int yy) {
+      return *reinterpret_cast<const _Float16*>(b + mom_row(yy, nx) + mom_f16(i, nx) + 2ull * xx);
+    };
+    _Float16 h[6];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    if constexpr (S::kCellShift)
-      f[i] = S::decode(src[pop_index(i, sx[i], sy[i], nx, ny)],
-                       src[rhat_row(sy[i], nx, ny) + (uint64_t)sx[i]], ws[i]);
-    else
-      f[i] = S::load(src + pop_index(i, sx[i], sy[i], nx, ny), ws[i] * rho0);
+    for (int i = 3; i < 9; ++i) h[i - 3] = H(i, x, y);
+    float own[9];
+    mom_decode(F(0, x, y), F(1, x, y), F(2, x, y), h, own);
+    f[0] = own[0];
+    f[1] = mom_a1(F(0, xm, y), F(1, xm, y), H(3, xm, y), H(5, xm, y), H(6, xm, y), H(7, xm, y),
+                  H(8, xm, y));
+    f[2] = mom_a2(F(0, x, ym), F(2, x, ym), H(4, x, ym), H(5, x, ym), H(6, x, ym), H(7, x, ym),
+                  H(8, x, ym));
+    f[3] = mom_pop(F(0, xp, y), H(3, xp, y), kW1);
+    f[4] = mom_pop(F(0, x, yp), H(4, x, yp), kW1);
+    f[5] = mom_pop(F(0, xm, ym), H(5, xm, ym), kW2);
+    f[6] = mom_pop(F(0, xp, ym), H(6, xp, ym), kW2);
+    f[7] = mom_pop(F(0, xp, yp), H(7, xp, yp), kW2);
+    f[8] = mom_pop(F(0, xm, yp), H(8, xm, yp), kW2);
+  } else {
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (S::kCellShift)
+        f[i] = S::decode(src[pop_index(i, sx[i], sy[i], nx, ny)],
+                         src[rhat_row(sy[i], nx, ny) + (uint64_t)sx[i]], ws[i]);
+      else
+        f[i] = S::load(src + pop_index(i, sx[i], sy[i], nx, ny), ws[i] * rho0);
+    }
   }
 }
 
@@ -1297,7 +1394,20 @@ template <class S>
 __device__ __forceinline__ void store_cell(typename S::T* dst, int nx, int ny, int x, int y,
                                            const float (&a)[9], float rho0) {
   const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
-  if constexpr (S::kCellShift) {
+  if constexpr (S::kMoment) {
+    // the record of values whose mass is their sum in index order
+    const float r = density(a);
+    float jx, jy;
+    _Float16 h[6];
+    mom_encode(a, r, jx, jy, h);
+    char* b = reinterpret_cast<char*>(dst) + mom_row(y, nx);
+    *reinterpret_cast<float*>(b + mom_f32(0, nx) + 4ull * x) = r;
+    *reinterpret_cast<float*>(b + mom_f32(1, nx) + 4ull * x) = jx;
+    *reinterpret_cast<float*>(b + mom_f32(2, nx) + 4ull * x) = jy;
+#pragma unroll
+    for (int i = 3; i < 9; ++i)
+      *reinterpret_cast<_Float16*>(b + mom_f16(i, nx) + 2ull * x) = h[i - 3];
+  } else if constexpr (S::kCellShift) {
     float r = a[0];
 #pragma unroll
     for (int i = 1; i < 9; ++i) r += a[i];
@@ -1648,30 +1758,46 @@ const void* step_fn_t() {
   return reinterpret_cast<const void*>(&k_step<S, NT, CPT, PF>);
 }
 
+// Moment storage runs the strip kernel only: its two-step and paired-column
+// shapes are not valid tiles (tile_valid) and have no kernel.
 template <class S, int NT, int PF, int W>
 hipError_t launch_fused_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                           int grid, int sub, hipStream_t st) {
-  hipLaunchKernelGGL((k_step2<S, NT, PF, W>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
-                     sub);
-  return hipGetLastError();
+  if constexpr (S::kMoment) {
+    return hipErrorInvalidDeviceFunction;
+  } else {
+    hipLaunchKernelGGL((k_step2<S, NT, PF, W>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
+                       sub);
+    return hipGetLastError();
+  }
 }
 
 template <class S, int NT, int PF, int W>
 const void* fused_fn_t() {
-  return reinterpret_cast<const void*>(&k_step2<S, NT, PF, W>);
+  if constexpr (S::kMoment)
+    return nullptr;
+  else
+    return reinterpret_cast<const void*>(&k_step2<S, NT, PF, W>);
 }
 
 template <class S, int NW, int PF>
 hipError_t launch_pair_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                          int grid, int sub, hipStream_t st) {
-  hipLaunchKernelGGL((k_step_pair<S, NW, PF>), dim3(grid), dim3(64 * NW), 0, st, descs, items,
-                     nitems, sub);
-  return hipGetLastError();
+  if constexpr (S::kMoment) {
+    return hipErrorInvalidDeviceFunction;
+  } else {
+    hipLaunchKernelGGL((k_step_pair<S, NW, PF>), dim3(grid), dim3(64 * NW), 0, st, descs, items,
+                       nitems, sub);
+    return hipGetLastError();
+  }
 }
 
 template <class S, int NW, int PF>
 const void* pair_fn_t() {
-  return reinterpret_cast<const void*>(&k_step_pair<S, NW, PF>);
+  if constexpr (S::kMoment)
+    return nullptr;
+  else
+    return reinterpret_cast<const void*>(&k_step_pair<S, NW, PF>);
 }
 
 using StepLauncher = hipError_t (*)(const InstDesc*, const TileItem*, const int*, int, int,
@@ -1742,7 +1868,8 @@ const void* step_fn(int storage, int variant) {
   switch (storage) {
     case 0: return kFn<StoreF32>[variant]();
     case 1: return kFn<StoreF16S>[variant]();
-    default: return kFn<StoreF16C>[variant]();
+    case 2: return kFn<StoreF16C>[variant]();
+    default: return kFn<StoreF16M>[variant]();
   }
 }
 }  // namespace
@@ -1752,12 +1879,15 @@ hipError_t launch_step(int storage, int variant, const InstDesc* descs, const Ti
   switch (storage) {
     case 0: return kLaunch<StoreF32>[variant](descs, items, nitems, grid, sub, st);
     case 1: return kLaunch<StoreF16S>[variant](descs, items, nitems, grid, sub, st);
-    default: return kLaunch<StoreF16C>[variant](descs, items, nitems, grid, sub, st);
+    case 2: return kLaunch<StoreF16C>[variant](descs, items, nitems, grid, sub, st);
+    default: return kLaunch<StoreF16M>[variant](descs, items, nitems, grid, sub, st);
   }
 }
 
 hipError_t step_occupancy(int storage, int variant, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, step_fn(storage, variant),
+  const void* fn = step_fn(storage, variant);
+  if (!fn) return hipErrorInvalidDeviceFunction;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, fn,
                                                       kVariants[variant].threads, 0);
 }
 
@@ -1800,13 +1930,14 @@ hipError_t graph_add_tick(hipGraph_t g, hipGraphNode_t* node, const hipGraphNode
 }
 
 // Calls f with a value of the storage trait numbered `storage` (LBM_F32,
-// LBM_F16_SHIFTED, LBM_F16_CELL).
+// LBM_F16_SHIFTED, LBM_F16_CELL, LBM_F16_MOMENT).
 template <class F>
 hipError_t with_storage(int storage, F&& f) {
   switch (storage) {
     case 0: return f(StoreF32{});
     case 1: return f(StoreF16S{});
-    default: return f(StoreF16C{});
+    case 2: return f(StoreF16C{});
+    default: return f(StoreF16M{});
   }
 }
 
@@ -1902,9 +2033,13 @@ hipError_t launch_step2_diag(int storage, const InstDesc* descs, const TileItem*
                              hipStream_t st) {
   const hipError_t e = with_storage(storage, [&](auto tag) {
     using S = decltype(tag);
-    hipLaunchKernelGGL(k_step2_diag<S>, dim3(grid), dim3(kDiag2Threads), 0, st, descs, items,
-                       nitems, sub, partials);
-    return hipGetLastError();
+    if constexpr (S::kMoment) {  // moment storage takes single steps only
+      return hipErrorInvalidDeviceFunction;
+    } else {
+      hipLaunchKernelGGL(k_step2_diag<S>, dim3(grid), dim3(kDiag2Threads), 0, st, descs, items,
+                         nitems, sub, partials);
+      return hipGetLastError();
+    }
   });
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kRedThreads), 0, st, (const double*)partials, grid,

@@ -35,8 +35,8 @@ constexpr int kNumTiles = kNumVariants * kNumRows;
 constexpr int kMinStripWidth = 64;
 constexpr int kMinRows = 2;
 
-// Storage forms (LBM_F32, LBM_F16_SHIFTED, LBM_F16_CELL).
-constexpr int kNumStorages = 3;
+// Storage forms (LBM_F32, LBM_F16_SHIFTED, LBM_F16_CELL, LBM_F16_MOMENT).
+constexpr int kNumStorages = 4;
 
 // Longest graph of batched steps (time steps per replay).
 constexpr int kMaxGraphSteps = 4096;

@@ -54,14 +54,18 @@ lbm_status validate_params(const lbm_params* p) {
     return fail(LBM_EINVAL, "grid too large (9 nx ny must be < 2^32)");
   if (!std::isfinite(p->G)) return fail(LBM_EINVAL, "G must be finite");
   if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return fail(LBM_EINVAL, "tau must be > 0.5");
-  if (p->storage != LBM_F32 && p->storage != LBM_F16_SHIFTED && p->storage != LBM_F16_CELL)
-    return fail(LBM_EINVAL, "storage must be LBM_F32, LBM_F16_SHIFTED or LBM_F16_CELL");
+  if (p->storage != LBM_F32 && p->storage != LBM_F16_SHIFTED && p->storage != LBM_F16_CELL &&
+      p->storage != LBM_F16_MOMENT)
+    return fail(LBM_EINVAL,
+                "storage must be LBM_F32, LBM_F16_SHIFTED, LBM_F16_CELL or LBM_F16_MOMENT");
   if (p->storage == LBM_F16_SHIFTED && (!std::isfinite(p->rho0) || p->rho0 < 0.0))
     return fail(LBM_EINVAL, "rho0 must be finite and >= 0");
   return LBM_OK;
 }
 
 size_t pop_bytes_for(const lbm_params& p) {
+  // moment storage: three FP32 and six FP16 values per cell
+  if (p.storage == LBM_F16_MOMENT) return 24ull * (size_t)p.nx * (size_t)p.ny;
   // per-cell-shift storage keeps a tenth plane (the reference density)
   const size_t planes = p.storage == LBM_F16_CELL ? 10 : 9;
   return planes * (size_t)p.nx * (size_t)p.ny * (p.storage == LBM_F32 ? 4 : 2);
@@ -183,6 +187,10 @@ int default_strip_tile(const lbm_params& p) {
 
 int default_tile(const lbm_params& p) {
   const size_t cells = (size_t)p.nx * (size_t)p.ny;
+  // Moment storage: strips of 256 threads x 1 cell, 2 rows in flight, with
+  // the band heights of the strip defaults.
+  if (p.storage == LBM_F16_MOMENT)
+    return find_variant(256, 1, 2, 0) * kNumRows + default_strip_tile(p) % kNumRows;
   // From a million cells up, two steps per launch: FP32 with 256 threads
   // writing 240 columns (64-byte-aligned strips), 8-row bands; FP16-shifted
   // from 16M cells with 256 threads, 2 rows in flight and balanced bands,
@@ -212,7 +220,7 @@ int default_tile(const lbm_params& p) {
   // grid allows it.
   if (p.storage != LBM_F32) {
     const int k = find_variant(256, 2, 2, 1) * kNumRows + row_choice(2);
-    if (tile_valid(k, p.nx)) return k;
+    if (tile_valid(k, p.nx, p.storage)) return k;
   }
   return default_strip_tile(p);
 }
@@ -471,10 +479,11 @@ lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int3
   for (int64_t j = 0; j < n;) {
     // The step that records the metrics, then the plain steps up to the next
     // record.  With at least one plain step to follow, the recording launch
-    // takes two steps.
+    // takes two steps (moment storage: always one).
     const int64_t plain = std::min<int64_t>(every - 1, n - j - 1);
     double* rec = d_srecords + (size_t)pending * 16;
-    if (plain >= 1) {
+    const bool two = plain >= 1 && p.storage != LBM_F16_MOMENT;
+    if (two) {
       SCLBM_HIP(launch_step2_diag(p.storage, d_desc, d_s2items, d_s2nitems, series2_nitems,
                                   parity, d_spartials, rec, stream));
       steps += 2;
@@ -488,7 +497,7 @@ lbm_status lbm_ctx::step_series(int64_t n, int32_t every, lbm_metrics* out, int3
       const lbm_status s = flush();
       if (s != LBM_OK) return s;
     }
-    const lbm_status s = advance(plain >= 1 ? plain - 1 : 0);
+    const lbm_status s = advance(two ? plain - 1 : plain);
     if (s != LBM_OK) return s;
     j += 1 + plain;
   }
@@ -760,7 +769,7 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
     }
   if (best < 0) return best;
   for (lbm_ctx* c : m)
-    if (c->p.storage == storage && !tile_batchable(best * kNumRows, c->p.nx))
+    if (c->p.storage == storage && !tile_batchable(best * kNumRows, c->p.nx, storage))
       return tile_variant(default_strip_tile(widest->p));
   return best;
 }
@@ -830,7 +839,7 @@ BatchShape batch_shape_max(const std::vector<lbm_ctx*>& m) {
   BatchShape b = batch_shape(m);
   for (int k = 0; k < kNumTiles; ++k) {
     bool valid = true;
-    for (lbm_ctx* c : m) valid = valid && tile_batchable(k, c->p.nx);
+    for (lbm_ctx* c : m) valid = valid && tile_batchable(k, c->p.nx, c->p.storage);
     if (!valid) continue;
     const BatchShape t = batch_shape(m, k);
     for (int s = 0; s < kNumStorages; ++s) {
@@ -899,7 +908,7 @@ lbm_status sclbm::create_ctx(const lbm_params* p, void* popA, void* popB, size_t
     return hip_fail(e, "descriptor upload");
   }
   int k = tuned_tile(*p, c->arch);
-  if (k < 0 || !tile_valid(k, p->nx)) k = default_tile(*p);
+  if (k < 0 || !tile_valid(k, p->nx, p->storage)) k = default_tile(*p);
   s = c->upload_tile(k);
   if (s != LBM_OK) {
     delete c;
@@ -1110,8 +1119,10 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
   return guarded("lbm_set_tile", [&]() -> lbm_status {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
-    if (!tile_valid(k, c->p.nx))
-      return fail(LBM_EINVAL, "paired-column tile shapes need an even nx >= 128");
+    if (!tile_valid(k, c->p.nx, c->p.storage))
+      return fail(LBM_EINVAL, c->p.storage == LBM_F16_MOMENT
+                                  ? "moment storage runs single-step strip tile shapes only"
+                                  : "paired-column tile shapes need an even nx >= 128");
     if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
     return c->upload_tile(k);
   });
@@ -1131,7 +1142,7 @@ lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
     double best_ms = 1e300;
     lbm_status st = LBM_OK;
     for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
-      if (!tile_valid(k, c->p.nx)) continue;
+      if (!tile_valid(k, c->p.nx, c->p.storage)) continue;
       st = c->upload_tile(k);
       if (st != LBM_OK) break;
       const int v = tile_variant(k);
@@ -1251,7 +1262,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
     lbm_status st = LBM_OK;
     for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
       bool valid = true;
-      for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx);
+      for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx, c->p.storage);
       if (!valid) continue;
       // Every member takes one step (two with a two-step shape) per launch from
       // its current buffer into its idle one, and the descriptors are not

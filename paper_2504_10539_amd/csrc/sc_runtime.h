@@ -76,13 +76,15 @@ inline int find_variant(int threads, int cells, int prefetch, int paired, int st
   }
   return -1;
 }
-// Whether tile shape k can run a grid nx columns wide.
-inline bool tile_valid(int k, int nx) {
+// Whether tile shape k can run a grid nx columns wide in this storage form
+// (moment storage runs single-step strip shapes only).
+inline bool tile_valid(int k, int nx, int storage) {
   const StepVariant& v = step_variant(tile_variant(k));
+  if (storage == LBM_F16_MOMENT && (v.paired || v.steps != 1)) return false;
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
 // Whether a batch can use tile shape k.
-inline bool tile_batchable(int k, int nx) { return tile_valid(k, nx); }
+inline bool tile_batchable(int k, int nx, int storage) { return tile_valid(k, nx, storage); }
 
 // Band height tile shape k uses on an nx x ny grid of this storage type
 // (balanced shapes: from the step kernel's occupancy on the current device).
@@ -126,10 +128,10 @@ int device_cu_count();
 struct BatchEngine {
   hipStream_t stream = nullptr;
   int K = 1, cap_inst = 0;
-  int cap_items[kNumStorages] = {}, variant[kNumStorages] = {-1, -1, -1},
+  int cap_items[kNumStorages] = {}, variant[kNumStorages] = {-1, -1, -1, -1},
       grid[kNumStorages] = {}, nitems[kNumStorages] = {};
   // tail launches of two-step storage types (capacity 0 otherwise)
-  int cap_titems[kNumStorages] = {}, tail_variant[kNumStorages] = {-1, -1, -1},
+  int cap_titems[kNumStorages] = {}, tail_variant[kNumStorages] = {-1, -1, -1, -1},
       tgrid[kNumStorages] = {};
   InstDesc* d_desc = nullptr;
   // Grid sized to the resident capacity, looping over the items (needed when

@@ -112,6 +112,33 @@ struct Done {
 
 constexpr int kMaxBypass = 64;  // a request may be passed at most this often
 
+// Step variants and table capacities of the continuous policy's batch engine.
+// Two-step strip variants, valid for every request width: 256-thread strips
+// suit the range of request sizes (64 .. 2048 columns) better than wider ones.
+// FP32 on 64-byte-aligned 240-column strips, the FP16 forms on 250-column
+// strips (per-cell shift with 2 rows in flight); a request up to 256 columns
+// wide is one periodic strip, and a tail launch takes the odd last step of a
+// tick.  Moment storage takes single-step strips of 256 threads, 2 rows in
+// flight.  Item capacity: every cell of the pool in the narrowest strips and
+// shortest bands, plus a margin per slot.
+struct EngineTables {
+  int cap_items[kNumStorages], cap_titems[kNumStorages], variants[kNumStorages];
+};
+EngineTables engine_tables(size_t pool_bytes, int max_slots) {
+  EngineTables t{};
+  const int v = find_variant(256, 1, 1, 0, 2, 240);
+  const int per = (int)std::min<size_t>(
+      pool_bytes / (36ull * tile_width(v * kNumRows) * kMinRows) + 64ull * max_slots, 1u << 22);
+  const int variants[kNumStorages] = {v, find_variant(256, 1, 1, 0, 2, 250),
+                                      find_variant(256, 1, 2, 0, 2, 250), find_variant(256, 1, 2, 0)};
+  for (int k = 0; k < kNumStorages; ++k) {
+    t.variants[k] = variants[k];
+    t.cap_items[k] = per;
+    t.cap_titems[k] = step_variant(variants[k]).steps == 2 ? per : 0;
+  }
+  return t;
+}
+
 size_t request_bytes(const lbm_params& p) {
   const WorkLayout w = work_layout(p.nx, p.ny);
   return 2 * align_up(pop_bytes_for(p), 256) + align_up(w.total, 256);
@@ -605,37 +632,18 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
     // (the fake executor keeps the same split, so its budget is the GPU
     // path's).
     size_t eng_bytes = 0;
+    EngineTables tab{};
     if (opts->policy == LBM_POLICY_CONTINUOUS) {
-      // Two-step strip variants, valid for every request width: 256-thread
-      // strips suit the range of request sizes (64 .. 2048 columns) better than
-      // wider ones.  FP32 on 64-byte-aligned 240-column strips, the FP16 forms
-      // on 250-column strips (per-cell shift with 2 rows in flight); a request
-      // up to 256 columns wide is one periodic strip, and a tail launch takes
-      // the odd last step of a tick.
-      const int v = find_variant(256, 1, 1, 0, 2, 240);
-      const int sw = tile_width(v * kNumRows);
-      const int per = (int)std::min<size_t>(pool_bytes / (36ull * sw * kMinRows) + 64ull * opts->max_slots,
-                                            1u << 22);
-      const int cap_items[kNumStorages] = {per, per, per};
-      const int cap_titems[kNumStorages] = {per, per, per};
-      const int variants[kNumStorages] = {v, find_variant(256, 1, 1, 0, 2, 250),
-                                          find_variant(256, 1, 2, 0, 2, 250)};
-      eng_bytes = align_up(
-          BatchEngine::work_bytes(opts->max_slots, cap_items, cap_titems, opts->steps_per_tick), 256);
+      tab = engine_tables(pool_bytes, opts->max_slots);
+      eng_bytes = align_up(BatchEngine::work_bytes(opts->max_slots, tab.cap_items, tab.cap_titems,
+                                                   opts->steps_per_tick),
+                           256);
       if (eng_bytes >= pool_bytes / 2) {
         delete s;
         return fail(LBM_ENOMEM, "pool too small for the batch tables");
       }
     }
     if (eng_bytes > 0 && !opts->fake_executor) {
-      const int v = find_variant(256, 1, 1, 0, 2, 240);
-      const int per = (int)std::min<size_t>(
-          pool_bytes / (36ull * tile_width(v * kNumRows) * kMinRows) + 64ull * opts->max_slots,
-          1u << 22);
-      const int cap_items[kNumStorages] = {per, per, per};
-      const int cap_titems[kNumStorages] = {per, per, per};
-      const int variants[kNumStorages] = {v, find_variant(256, 1, 1, 0, 2, 250),
-                                          find_variant(256, 1, 2, 0, 2, 250)};
       s->eng.persistent = true;
       s->eng.lazy_storages = true;  // no empty launches for storage types not yet served
       // One band height for every request: the persistent grid hands items out
@@ -643,8 +651,9 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
       // saturated FP32 trace 4, 8, 16 and 32 rows served 92k, 101k, 104k and
       // 104k MLUPS.
       s->eng.row_override = row_choice(16);
-      lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, cap_items,
-                                 cap_titems, variants, s->pool + pool_bytes - eng_bytes, eng_bytes);
+      lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, tab.cap_items,
+                                 tab.cap_titems, tab.variants, s->pool + pool_bytes - eng_bytes,
+                                 eng_bytes);
       if (r != LBM_OK) {
         s->eng.destroy();
         delete s;

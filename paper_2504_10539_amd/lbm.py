@@ -31,6 +31,7 @@ LBM_EBUSY = -7
 LBM_F32 = 0
 LBM_F16_SHIFTED = 1
 LBM_F16_CELL = 2
+LBM_F16_MOMENT = 3
 LBM_POLICY_CONTINUOUS = 0
 LBM_POLICY_FIFO = 1
 

@@ -1,0 +1,207 @@
+"""FP16 storage with exact conserved moments (LBM_F16_MOMENT) against the FP64 oracle.
+
+Storage form: a cell x keeps the record of the nine values A_i(x) it wrote:
+its density rho (FP32; the record's mass), the momentum jx, jy of the A_i
+(FP32), and h_i = half_RNE(fma(-w_i, rho, A_i)) for i = 3..8.  Read back:
+A_i = fma(rho, w_i, h_i) for i >= 3, A_1 = (jx + A_3) - ((A_5 - A_7) + (A_8 - A_6)),
+A_2 = (jy + A_4) - ((A_5 - A_7) - (A_8 - A_6)), A_0 = rho - (the other eight).
+Mass and momentum therefore pass between cells at FP32 rounding; only the
+non-conserved moments round to half precision, and the BGK collision of
+Eq. (1) relaxes those instead of carrying the rounding on.  This is the form
+that meets the FP16 density bar (1e-3 in both readings) on the 64^2 droplet.
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2504_10539_amd import inputs
+from tests.gpu_helpers import f32_state, lbm, need_gpu, set_state_from, to_np
+
+pytestmark = pytest.mark.gpu
+
+EX = [0, 1, 0, -1, 0, 1, -1, -1, 1]
+EY = [0, 0, 1, 0, -1, 1, 1, -1, -1]
+W = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4, dtype=np.float32)
+f32 = np.float32
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    need_gpu()
+
+
+def _round_f32(q: Fraction) -> np.float32:
+    """Nearest FP32 to the exact value q, ties to even."""
+    c = np.float32(float(q))
+    best = None
+    for v in (np.nextafter(c, np.float32(-np.inf)), c, np.nextafter(c, np.float32(np.inf))):
+        d = abs(Fraction(float(v)) - q)
+        if best is None or d < best[0] or (d == best[0] and (v.view(np.uint32) & 1) == 0):
+            best = (d, v)
+    return best[1]
+
+
+def _fma32(a, b, c) -> np.float32:
+    return _round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
+
+
+def _expected_roundtrip(f):
+    """get_state(set_state(f)) in the moment form, computed exactly on the host:
+    FP32 sums and differences in numpy (IEEE, round to nearest even), the fused
+    multiply-adds in exact rational arithmetic rounded once."""
+    A = np.stack([np.roll(f[i], (-EY[i], -EX[i]), axis=(0, 1)) for i in range(9)])  # A_i(x) = f_i(x + e_i)
+    ny, nx = A.shape[1:]
+    rho = A[0].copy()
+    for i in range(1, 9):
+        rho = (rho + A[i]).astype(f32)
+    a, b = (A[5] - A[7]).astype(f32), (A[8] - A[6]).astype(f32)
+    jx = ((A[1] - A[3]).astype(f32) + (a + b).astype(f32)).astype(f32)
+    jy = ((A[2] - A[4]).astype(f32) + (a - b).astype(f32)).astype(f32)
+    dec = np.empty_like(A)
+    for y in range(ny):
+        for x in range(nx):
+            r = rho[y, x]
+            for i in range(3, 9):
+                h = np.float16(_fma32(-W[i], r, A[i, y, x]))
+                dec[i, y, x] = _fma32(r, W[i], np.float32(h))
+    d, e = (dec[5] - dec[7]).astype(f32), (dec[8] - dec[6]).astype(f32)
+    dec[1] = ((jx + dec[3]).astype(f32) - (d + e).astype(f32)).astype(f32)
+    dec[2] = ((jy + dec[4]).astype(f32) - (d - e).astype(f32)).astype(f32)
+    s = (((dec[1] + dec[3]).astype(f32) + (dec[2] + dec[4]).astype(f32)).astype(f32) +
+         ((dec[5] + dec[7]).astype(f32) + (dec[6] + dec[8]).astype(f32)).astype(f32)).astype(f32)
+    dec[0] = (rho - s).astype(f32)
+    return np.stack([np.roll(dec[i], (EY[i], EX[i]), axis=(0, 1)) for i in range(9)])
+
+
+def test_storage_roundtrip_is_the_moment_record():
+    L = lbm()
+    f = f32_state(inputs.random_positive_state(20, 12, seed=3)).astype(np.float32)
+    sim = L.Simulation(20, 12, -5.0, 1.0, L.LBM_F16_MOMENT)
+    set_state_from(sim, f)
+    got = sim.get_state().cpu().numpy()
+    assert np.array_equal(got.view(np.uint32), _expected_roundtrip(f).view(np.uint32))
+
+
+def test_config1_fp16_moment_meets_the_density_bar():
+    """Config 1 (64^2 droplet, G -5, tau 1, 1000 steps): density within 1e-3 of
+    the FP64 oracle in both readings, every metric within 2%."""
+    L = lbm()
+    N = 64
+    drops = inputs.single_droplet(N, 16)
+    sim = L.Simulation(N, N, -5.0, 1.0, L.LBM_F16_MOMENT).init_droplets(drops, seed=1)
+    sim.step(1000)
+    rho = to_np(sim.moments()[0])
+    m = sim.metrics()
+    ref = oracle.step(oracle.droplet_state(N, N, drops, seed=1), -5.0, 1.0, 1000, 8)
+    rho_ref = oracle.density(ref)
+    mref = oracle.metrics(rho_ref)
+    err_range = float(np.max(np.abs(rho - rho_ref)) / rho_ref.max())
+    err_cell = float(np.max(np.abs(rho - rho_ref) / rho_ref))
+    rel = {k: abs(m[k] / mref[k] - 1) for k in ("Gmax", "drho", "W_eff", "E_int")}
+    print(f"fp16 moment: max|drho|/max rho = {err_range:.2e}, per-cell max|drho|/rho = "
+          f"{err_cell:.2e}, metric errors {rel}, mass drift "
+          f"{m['mass'] / oracle.conservation(ref)[0] - 1:.2e}")
+    assert err_range <= 1e-3
+    assert err_cell <= 1e-3
+    for k, v in rel.items():
+        assert v <= 0.02, k
+    assert abs(m["W"] - mref["W"]) <= 0.02 * mref["W"]
+
+
+def test_mass_and_momentum_pass_at_fp32_rounding():
+    """A random state carrying momentum: total mass and momentum after 200 steps
+    stay at FP32 rounding level (the pairwise force conserves momentum), where
+    the single-shift FP16 form moves them by orders of magnitude more."""
+    L = lbm()
+    nx, ny = 96, 80
+    rho = oracle.init_density(nx, ny, [(40.0, 36.0, 14.0), (75.0, 60.0, 9.0)], 2.0, 0.15, 2.0,
+                              1e-3, 9)
+    f0 = f32_state(oracle.equilibrium(1.0, 0.03, -0.02)[:, None, None] * rho[None])
+    c0 = oracle.conservation(f0)
+    drift = {}
+    for storage in (L.LBM_F16_MOMENT, L.LBM_F16_SHIFTED):
+        sim = L.Simulation(nx, ny, -5.0, 1.0, storage, 1.0)
+        set_state_from(sim, f0)
+        sim.step(200)
+        c = oracle.conservation(to_np(sim.get_state()))
+        drift[storage] = [abs(c[k] - c0[k]) / c0[0] for k in range(3)]
+    print("relative drift of (mass, mom_x, mom_y):", drift)
+    assert max(drift[L.LBM_F16_MOMENT]) < 2e-6
+    assert max(drift[L.LBM_F16_SHIFTED]) > 10 * max(drift[L.LBM_F16_MOMENT])
+
+
+def test_moment_tile_shapes_bitwise_identical():
+    """Every strip shape computes bitwise the same state; the shapes moment
+    storage does not run (two-step, paired) are refused."""
+    L = lbm()
+    nx, ny = 300, 77
+    f0 = f32_state(oracle.droplet_state(nx, ny, [(150.0, 38.0, 20.0), (20.0, 70.0, 9.0)], seed=6))
+    ref = None
+    sim = L.Simulation(nx, ny, -5.5, 0.8, L.LBM_F16_MOMENT)
+    for t in L.tiles():
+        if t["steps"] != 1 or t["paired"]:
+            with pytest.raises(L.LbmError) as e:
+                sim.set_tile(t["id"])
+            assert e.value.code == L.LBM_EINVAL
+            continue
+        sim.set_tile(t["id"])
+        set_state_from(sim, f0)
+        sim.step(5)
+        got = to_np(sim.get_state())
+        if ref is None:
+            ref = got
+        assert np.array_equal(got, ref), t
+
+
+def test_moment_steps_match_the_oracle_one_step_at_a_time():
+    """From a state the storage holds exactly, one step equals the FP64 oracle up
+    to FP32 arithmetic and the half rounding of the six stored deviations."""
+    L = lbm()
+    nx, ny = 48, 40
+    f = oracle.droplet_state(nx, ny, [(20.0, 22.0, 9.0)], seed=4)
+    sim = L.Simulation(nx, ny, -5.0, 0.9, L.LBM_F16_MOMENT)
+    set_state_from(sim, f)
+    f0 = to_np(sim.get_state())  # the state as the storage holds it
+    sim.step(1)
+    got = to_np(sim.get_state())
+    ref = oracle.step(f0, -5.0, 0.9, 1)
+    # a stored deviation of up to ~0.05 rounds by up to ~1.2e-5; A_1, A_2 and A_0
+    # take up to five of those, and a cell's density collects values of nine records
+    dp = np.abs(got - ref).max()
+    dr = np.abs(oracle.density(got) - oracle.density(ref)).max()
+    print(f"one step: max |df| = {dp:.2e}, max |drho| = {dr:.2e}")
+    assert dp <= 2e-4 and dr <= 2e-4
+
+
+def test_moment_in_a_mixed_batch_is_bitwise():
+    L = lbm()
+    mk = [lambda: L.Simulation(96, 64, -5.0, 1.0, L.LBM_F16_MOMENT).init_droplets([(40, 30, 14)], seed=2),
+          lambda: L.Simulation(80, 80, -5.5, 0.9, L.LBM_F32).init_droplets([(40, 40, 15)], seed=3),
+          lambda: L.Simulation(130, 50, -5.0, 1.0, L.LBM_F16_CELL).init_droplets([(60, 25, 12)], seed=4)]
+    batch = [m() for m in mk]
+    solo = [m() for m in mk]
+    bt = L.Batch(batch, steps_per_graph=16)
+    bt.step(53)
+    for s in solo:
+        s.step(53)
+    for a, s in zip(batch, solo):
+        assert np.array_equal(to_np(a.get_state()), to_np(s.get_state()))
+    bt.close()
+
+
+def test_moment_series_records_equal_separate_passes():
+    L = lbm()
+    N = 96
+    a = L.Simulation(N, N, -5.0, 1.0, L.LBM_F16_MOMENT).init_droplets(inputs.single_droplet(N, 24), seed=5)
+    b = L.Simulation(N, N, -5.0, 1.0, L.LBM_F16_MOMENT).init_droplets(inputs.single_droplet(N, 24), seed=5)
+    recs = a.step_series(40, 7)
+    assert len(recs) == 6
+    for k, r in enumerate(recs):
+        m = b.metrics()
+        assert r["step"] == m["step"] == 7 * k
+        assert r["n_above"] == m["n_above"] and r["Gmax"] == m["Gmax"]
+        assert abs(r["E_int"] - m["E_int"]) <= 1e-12 * m["E_int"]
+        b.step(7 if k < 5 else 5)
+    assert np.array_equal(to_np(a.get_state()), to_np(b.get_state()))

@@ -34,6 +34,7 @@ REQS = [  # nx, G, tau, steps, drops, storage
     (200, -5.0, 1.0, 33, [(100, 100, 30)], 1),
     (128, -6.0, 0.7, 130, [(64, 64, 20)], 0),
     (140, -5.0, 1.0, 75, [(70, 70, 20)], 2),
+    (120, -5.0, 1.0, 61, [(60, 60, 18)], 3),
 ]
 
 

@@ -11,7 +11,9 @@ kernel defect; an FP32-ulp perturbation of the FP64 run grows only to 1.8e-6,
 i.e. the field itself does not amplify rounding noise.
 FP16-shifted storage keeps every metric within 0.9%, while the droplets
 drift apart from the FP64 run (per-cell density errors of order one by step
-2000); the density bar does not hold for this workload.
+2000); the density bar does not hold for this workload.  The exact-moment FP16
+form (LBM_F16_MOMENT) stays within 1.5e-4 on every metric and ends at 1.07e-3
+of rho_max (3.0e-3 per cell), ten times closer than the per-cell shift.
 """
 import numpy as np
 import pytest
@@ -39,12 +41,13 @@ def window_series(nthreads):
     f = oracle.droplet_state(n, n, drops, seed=3, period=(4096, 4096))
     sims = {"f32": L.Simulation(n, n, G, tau, L.LBM_F32),
             "f16": L.Simulation(n, n, G, tau, L.LBM_F16_SHIFTED, 1.0),
-            "f16c": L.Simulation(n, n, G, tau, L.LBM_F16_CELL)}
+            "f16c": L.Simulation(n, n, G, tau, L.LBM_F16_CELL),
+            "f16m": L.Simulation(n, n, G, tau, L.LBM_F16_MOMENT)}
     for s in sims.values():
         s.init_droplets(drops, seed=3, period=(4096, 4096))
     worst = {"f32_cell": 0.0, "f32_range": 0.0, "f32_metric": 0.0, "f16_metric": 0.0,
              "f16_cell": 0.0, "f16_range": 0.0, "f16c_metric": 0.0, "f16c_range": 0.0,
-             "f16c_cell": 0.0}
+             "f16c_cell": 0.0, "f16m_metric": 0.0, "f16m_range": 0.0, "f16m_cell": 0.0}
     for seg in range(1, 11):
         f = oracle.step(f, G, tau, 500, nthreads)
         rr = oracle.density(f)
@@ -68,9 +71,9 @@ def window_series(nthreads):
                 worst["f16_cell"] = max(worst["f16_cell"], cell)
                 worst["f16_range"] = max(worst["f16_range"], rng)
             else:
-                worst["f16c_metric"] = max(worst["f16c_metric"], met)
-                worst["f16c_range"] = max(worst["f16c_range"], rng)
-                worst["f16c_cell"] = max(worst["f16c_cell"], cell)
+                worst[f"{name}_metric"] = max(worst[f"{name}_metric"], met)
+                worst[f"{name}_range"] = max(worst[f"{name}_range"], rng)
+                worst[f"{name}_cell"] = max(worst[f"{name}_cell"], cell)
         print(" | ".join(line))
     print("worst", worst)
     return worst
@@ -84,13 +87,17 @@ def test_many_droplet_window_error_series(window_series):
     assert worst["f16_metric"] < 0.02, worst
     assert worst["f16c_metric"] < 0.02, worst
     assert worst["f16c_range"] < 2e-2, worst  # measured 1.3e-2 at step 5000
+    assert worst["f16m_metric"] < 0.02, worst
 
 
 @pytest.mark.xfail(strict=True, reason="the FP16 density bar (1e-3) is not met on this chaotic "
                    "2000-droplet window: FP16-shifted storage lets the droplets drift apart from "
-                   "the FP64 run (order-one per-cell errors from step 2000) and the per-cell shift "
-                   "reaches 1.3e-2 of rho_max by step 5000")
-@pytest.mark.parametrize("form", ["f16", "f16c"])
+                   "the FP64 run (order-one per-cell errors from step 2000), the per-cell shift "
+                   "reaches 1.3e-2 of rho_max by step 5000, and even the exact-moment form, "
+                   "whose rounding never touches mass or momentum, ends at 1.07e-3 of rho_max "
+                   "and 3.0e-3 per cell: coalescing droplets amplify its half-precision noise "
+                   "(FP32 itself reaches 7.5e-5 per cell here)")
+@pytest.mark.parametrize("form", ["f16", "f16c", "f16m"])
 def test_many_droplet_window_fp16_density_bar(window_series, form):
     assert window_series[f"{form}_range"] <= 1e-3
     assert window_series[f"{form}_cell"] <= 1e-3
