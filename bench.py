@@ -242,12 +242,15 @@ def run_paper_preset(args, torch, lbm):
     segments) on a 256^2 grid, with the FP16-shifted fork from the common state."""
     from paper_2504_10539_amd import preset
     t0 = time.perf_counter()
-    r = preset.run(nx=256, segment=500, every=50, fork_storage=lbm.LBM_F16_SHIFTED)
+    r = preset.run(nx=256, segment=500, every=50, fork_storage=lbm.LBM_F16_SHIFTED, pinn_beta=0.5)
     torch.cuda.synchronize()
     res = {"workload": "paper_droplet_256", "steps": 500 + 5 * 500, "wall_s": time.perf_counter() - t0,
            "table_I": r["table_I"], "table_II": r["table_II"],
-           "fp16_fork": {"table_I": r["fork"]["table_I"], "table_II": r["fork"]["table_II"]}}
-    log(f"[paper preset 256^2] table I {res['table_I']}, table II {res['table_II']}")
+           "fp16_fork": {"table_I": r["fork"]["table_I"], "table_II": r["fork"]["table_II"]},
+           "pinn_lbm": {"beta": r["pinn"]["beta"], "table_I": r["pinn"]["table_I"],
+                        "table_II": r["pinn"]["table_II"]}}
+    log(f"[paper preset 256^2] pure LBM: table I {res['table_I']}, table II {res['table_II']}; "
+        f"PINN-LBM: table I {res['pinn_lbm']['table_I']}, table II {res['pinn_lbm']['table_II']}")
     return res
 
 
@@ -275,6 +278,78 @@ def run_one_step_reference(args, torch, lbm, inputs):
     return {"kernel": kernel_name(lbm, tile, lbm.LBM_F32), "tile": tile,
             "launch_ms": round(ms, 5), "achieved": round(gbs, 1),
             "frac": round(gbs / HBM_PEAK_GBS, 4)}
+
+
+# Matrix-core flops per cell of the PINN inference: the dense layers 2-4
+# (64 x 128, 128 x 128 and 128 x 64 multiply-adds).
+PINN_MFMA_FLOPS = 2 * (64 * 128 + 128 * 128 + 128 * 64)
+FP16_MFMA_PEAK_TFLOPS = 2500.0
+
+
+def run_pinn(args, torch, lbm, inputs):
+    """The PINN surrogate (Sec. II-B/III-B network) on a grid of the bench size:
+    inference at every cell (lbm_pinn_infer) and the Sec. II-C correction
+    (lbm_pinn_correct, interface cells only) of the paper's droplet (Sec. III-A:
+    R = nx / 6, G -5.5, tau 1.0) after --pinn-steps FP32 steps, timed with HIP
+    events.  The network is first trained on the state's own fields (Sec. III-B:
+    300 epochs, learning rate 3e-4, PyTorch on the GPU; not part of the timed
+    path).  A single droplet is the workload the surrogate is made for: a
+    smooth network cannot represent the 2000-droplet field."""
+    from paper_2504_10539_amd import pinn
+    N = args.n
+    sim = lbm.Simulation(N, N, -5.5, 1.0, lbm.LBM_F32)
+    sim.init_droplets(inputs.single_droplet(N, N / 6.0), seed=1)
+    sim.step(args.pinn_steps)
+    net = pinn.make_net(seed=0, device="cuda")
+    t0 = time.perf_counter()
+    hist = pinn.train(net, pinn.state_fields(sim), args.G, args.tau, epochs=args.pinn_epochs, seed=0)
+    train_s = time.perf_counter() - t0
+    params = pinn.pack(net)
+    out = [torch.empty((N, N), dtype=torch.float32, device="cuda") for _ in range(3)]
+    stream = torch.cuda.current_stream()
+
+    def infer():
+        lbm.LIB.lbm_pinn_infer(sim.handle, params.data_ptr(), *[o.data_ptr() for o in out])
+
+    infer()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        infer()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    infer_ms = e0.elapsed_time(e1) / reps
+    mask = torch.zeros(N * N, dtype=torch.uint8, device="cuda")
+    sim.pinn_correct(params, 0.5, mask)
+    torch.cuda.synchronize()
+    corrected = int(mask.sum().item())
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(reps):
+        sim.pinn_correct(params, 0.5)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    correct_ms = c0.elapsed_time(c1) / reps
+    finite = sim.metrics()["finite"]
+    sim.close()
+    del out, mask
+    torch.cuda.empty_cache()
+    tflops = PINN_MFMA_FLOPS * N * N / (infer_ms * 1e-3) / 1e12
+    res = {"workload": f"paper_droplet_{N}", "cells": N * N, "steps_before": args.pinn_steps,
+           "infer_ms": infer_ms, "infer_mcells_per_s": N * N / (infer_ms * 1e-3) / 1e6,
+           "mfma_flops_per_cell": PINN_MFMA_FLOPS, "mfma_tflops": tflops,
+           "mfma_peak_tflops": FP16_MFMA_PEAK_TFLOPS, "mfma_frac": tflops / FP16_MFMA_PEAK_TFLOPS,
+           "correct_ms": correct_ms, "corrected_cells": corrected,
+           "corrected_fraction": corrected / (N * N), "finite_after": finite,
+           "train_epochs": args.pinn_epochs, "train_s": train_s,
+           "train_loss": [hist[0], hist[-1]],
+           "kernel": "k_pinn<StoreF32, true>"}
+    log(f"[pinn] inference {infer_ms:.2f} ms for {N}^2 cells ({tflops:.0f} TFLOP/s on the matrix "
+        f"cores, {tflops / FP16_MFMA_PEAK_TFLOPS:.3f} of FP16 peak); correction {correct_ms:.2f} ms, "
+        f"{corrected} interface cells")
+    return res
 
 
 def run_copy_reference(torch, lbm):
@@ -495,7 +570,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--c2-steps", type=int, default=10000)
-    ap.add_argument("--only", choices=["single_droplet_1024", "serving"], default=None,
+    ap.add_argument("--pinn-steps", type=int, default=500)
+    ap.add_argument("--pinn-epochs", type=int, default=300)
+    ap.add_argument("--only", choices=["single_droplet_1024", "serving", "pinn"], default=None,
                     help="run one extra workload alone and print its result (for profiling)")
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--sweep-instances", type=int, default=512)
@@ -531,6 +608,9 @@ def main():
         return
     if args.only == "serving":
         print(json.dumps(run_serving(args, torch, lbm, inputs)), flush=True)
+        return
+    if args.only == "pinn":
+        print(json.dumps(run_pinn(args, torch, lbm, inputs)), flush=True)
         return
     log(f"device {torch.cuda.get_device_name(0)}; workload {args.n}^2, {args.drops} droplets, "
         f"G {args.G}, tau {args.tau}, {args.lbm_steps} LBM steps per job")
@@ -582,6 +662,7 @@ def main():
         line["paper_preset"] = run_paper_preset(args, torch, lbm)
         line["metric_series"] = run_series_cost(args, torch, lbm, inputs)
         line["sweep_512x256"] = run_sweep(args, torch, lbm, inputs)
+        line["pinn"] = run_pinn(args, torch, lbm, inputs)
         line["serving"] = run_serving(args, torch, lbm, inputs)
         if not args.no_cpu:
             line["cpu_baseline"] = run_cpu_baseline(args, inputs)

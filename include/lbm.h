@@ -384,6 +384,44 @@ double lbm_server_clock(const lbm_server* s);
 /* Stops the scheduler after draining, then releases host state. */
 lbm_status lbm_server_destroy(lbm_server* s);
 
+/* ------------------------------------------------------------ PINN surrogate */
+
+/* The network of Sec. III-B: inputs (x, y), hidden layers of 64, 128, 128
+ * and 64 neurons with tanh, a linear output layer giving (rho, u_x, u_y)
+ * (Sec. II-B, Eq. (2)).  Its parameters are one device array of
+ * LBM_PINN_PARAMS FP32 values: for each layer l = 1..5 in order, W_l
+ * row-major with shape (out, in) (a layer maps h to W_l h + b_l), then b_l.
+ * The input of cell (x, y) is its centre scaled to (-1, 1):
+ * ((2 x + 1) / nx - 1, (2 y + 1) / ny - 1).  Layers 2 to 4 run on the matrix
+ * cores with their weights and inputs rounded to FP16 and FP32 accumulation;
+ * layers 1 and 5 and tanh are FP32.  The hidden activations are rounded to
+ * FP16 between layers, so an output differs from the same network in exact
+ * arithmetic by at most ||W_5|| (2^-11 sqrt(64) + ||W_4|| (2^-11 sqrt(128) +
+ * ||W_3|| (2^-11 sqrt(128) + ||W_2|| 2^-11 sqrt(64)))) (spectral norms of the
+ * FP16-rounded weights) plus FP32 rounding. */
+#define LBM_PINN_PARAMS 33475
+
+/* The network's fields at every cell of the run's grid: rho_N, u_x and u_y
+ * into caller device arrays of nx * ny floats (row-major; any may be NULL).
+ * `params` is a device array of LBM_PINN_PARAMS floats (4-byte aligned).
+ * Does not touch the state.  Asynchronous. */
+lbm_status lbm_pinn_infer(lbm_ctx* ctx, const float* params, float* rho, float* ux, float* uy);
+
+/* The correction of Sec. II-C, applied to the current state at its interface
+ * cells: the cells with |grad rho| > 0.01 (Eq. (9), the Eq. (16) gradient
+ * with periodic wrap, rho in FP64 from the stored populations).  On such a
+ * cell, with rho and u = sum_i f_i e_i / rho of its populations and the
+ * network's rho_N, u_N: rho' = rho + beta (rho_N - rho), u' = u + beta
+ * (u_N - u), and f_i becomes f_i + f_eq_i(rho', u') - f_eq_i(rho, u) (FP32),
+ * stored back in the run's storage form; every other cell is left bitwise as
+ * it was.  beta in [0, 1].  `mask` (optional caller device array of nx * ny
+ * bytes) receives 1 for the corrected cells, 0 elsewhere.  Uses the idle
+ * population buffer as scratch.  LBM_EINVAL for LBM_F16_MOMENT (its records
+ * hold no single value per population to rewrite), a bad beta or a NULL or
+ * misaligned params; LBM_EBUSY for a member of a live batch.
+ * Asynchronous. */
+lbm_status lbm_pinn_correct(lbm_ctx* ctx, const float* params, double beta, uint8_t* mask);
+
 /* ------------------------------------------------------------ measurement */
 
 /* Device-to-device copy of `bytes` (multiple of 16) with a plain streaming

@@ -18,7 +18,7 @@ OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libsclbm.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["sc_kernels.hip", "sc_runtime.cpp", "sc_server.cpp", "sc_noalloc.hip"]
+SOURCES = ["sc_kernels.hip", "sc_runtime.cpp", "sc_server.cpp", "sc_noalloc.hip", "sc_pinn.hip"]
 ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -370,4 +370,76 @@ __device__ __forceinline__ void collide(float f[9], float rho, float Fx, float F
   for (int i = 0; i < 9; ++i) f[i] = fmaf(omega, feq[i] - f[i], f[i]);
 }
 
+
+// ------------------------------------------------------------------ one cell at a time
+
+// Pre-collision populations at cell (x, y), pulled from a buffer.
+template <class S>
+__device__ __forceinline__ void pull_cell(const typename S::T* src, size_t n, int nx, int ny, int x,
+                                          int y, float rho0, float f[9]) {
+  (void)n;
+  const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+  const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+  if constexpr (S::kMoment) {
+    const char* b = reinterpret_cast<const char*>(src);
+    auto F = [&](int k, int xx, int yy) {
+      return *reinterpret_cast<const float*>(b + mom_row(yy, nx) + mom_f32(k, nx) + 4ull * xx);
+    };
+    auto H = [&](int i, int xx, int yy) {
+      return *reinterpret_cast<const _Float16*>(b + mom_row(yy, nx) + mom_f16(i, nx) + 2ull * xx);
+    };
+    _Float16 h[6];
+#pragma unroll
+    for (int i = 3; i < 9; ++i) h[i - 3] = H(i, x, y);
+    float own[9];
+    mom_decode(F(0, x, y), F(1, x, y), F(2, x, y), h, own);
+    f[0] = own[0];
+    f[1] = mom_a1(F(0, xm, y), F(1, xm, y), H(3, xm, y), H(5, xm, y), H(6, xm, y), H(7, xm, y),
+                  H(8, xm, y));
+    f[2] = mom_a2(F(0, x, ym), F(2, x, ym), H(4, x, ym), H(5, x, ym), H(6, x, ym), H(7, x, ym),
+                  H(8, x, ym));
+    f[3] = mom_pop(F(0, xp, y), H(3, xp, y), kW1);
+    f[4] = mom_pop(F(0, x, yp), H(4, x, yp), kW1);
+    f[5] = mom_pop(F(0, xm, ym), H(5, xm, ym), kW2);
+    f[6] = mom_pop(F(0, xp, ym), H(6, xp, ym), kW2);
+    f[7] = mom_pop(F(0, xp, yp), H(7, xp, yp), kW2);
+    f[8] = mom_pop(F(0, xm, yp), H(8, xm, yp), kW2);
+  } else {
+    const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+    const int sx[9] = {x, xm, x, xp, x, xm, xp, xp, xm};
+    const int sy[9] = {y, y, ym, y, yp, ym, ym, yp, yp};
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      if constexpr (S::kCellShift)
+        f[i] = S::decode(src[pop_index(i, sx[i], sy[i], nx, ny)],
+                         src[rhat_row(sy[i], nx, ny) + (uint64_t)sx[i]], ws[i]);
+      else
+        f[i] = S::load(src + pop_index(i, sx[i], sy[i], nx, ny), ws[i] * rho0);
+    }
+  }
+}
+
+
+// Writes v as the stored value a pull of population i at cell (x, y) reads,
+// A_i(x - e_i), rounded as the storage form rounds it (per-cell-shift
+// storage: with the reference density of the cell that holds it, which is
+// kept).  Moment storage keeps whole records and has no single stored value
+// per population; it is not written this way.
+template <class S>
+__device__ __forceinline__ void store_pulled(typename S::T* dst, int nx, int ny, int x, int y,
+                                             int i, float v, float rho0) {
+  static_assert(!S::kMoment, "moment records are written whole");
+  const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+  const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+  const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
+  int sx = x - ex[i], sy = y - ey[i];
+  sx = sx < 0 ? sx + nx : (sx >= nx ? sx - nx : sx);
+  sy = sy < 0 ? sy + ny : (sy >= ny ? sy - ny : sy);
+  const uint64_t at = pop_index(i, sx, sy, nx, ny);
+  if constexpr (S::kCellShift)
+    dst[at] = S::encode(v, dst[rhat_row(sy, nx, ny) + (uint64_t)sx], ws[i]);
+  else
+    dst[at] = S::pack(v, ws[i] * rho0);
+}
+
 }  // namespace sclbm

@@ -32,6 +32,7 @@ LBM_F32 = 0
 LBM_F16_SHIFTED = 1
 LBM_F16_CELL = 2
 LBM_F16_MOMENT = 3
+LBM_PINN_PARAMS = 33475
 LBM_POLICY_CONTINUOUS = 0
 LBM_POLICY_FIFO = 1
 
@@ -116,6 +117,8 @@ _PROTOS = {
     "lbm_moments": (_i32, [_vp, _vp, _vp, _vp]),
     "lbm_interface_metrics": (_i32, [_vp, _P(lbm_metrics)]),
     "lbm_interface_metrics_noalloc": (_i32, [_vp, _vp]),
+    "lbm_pinn_infer": (_i32, [_vp, _vp, _vp, _vp, _vp]),
+    "lbm_pinn_correct": (_i32, [_vp, _vp, ctypes.c_double, _vp]),
     "lbm_get_state": (_i32, [_vp, _vp]),
     "lbm_set_state": (_i32, [_vp, _vp]),
     "lbm_step_count": (_i64, [_vp]),
@@ -341,6 +344,27 @@ class Simulation:
         _check(LIB.lbm_step_series(self.handle, int(n), int(every), out, cap, ctypes.byref(cnt)),
                "lbm_step_series")
         return [out[k].as_dict() for k in range(cnt.value)]
+
+    def pinn_infer(self, params):
+        """The network's (rho, u_x, u_y) at every cell; `params` is a device
+        tensor of LBM_PINN_PARAMS floats (see include/lbm.h)."""
+        torch = _torch()
+        assert params.dtype == torch.float32 and params.numel() == LBM_PINN_PARAMS
+        out = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+               for _ in range(3)]
+        _check(LIB.lbm_pinn_infer(self.handle, _dev_ptr(params), *[_dev_ptr(o) for o in out]),
+               "lbm_pinn_infer")
+        return tuple(out)
+
+    def pinn_correct(self, params, beta: float, mask=None):
+        """Sec. II-C correction of the state at its interface cells (in place)."""
+        torch = _torch()
+        assert params.dtype == torch.float32 and params.numel() == LBM_PINN_PARAMS
+        if mask is not None:
+            assert mask.dtype == torch.uint8 and mask.numel() == self.nx * self.ny
+        _check(LIB.lbm_pinn_correct(self.handle, _dev_ptr(params), float(beta), _dev_ptr(mask)),
+               "lbm_pinn_correct")
+        return self
 
     def get_state(self):
         torch = _torch()

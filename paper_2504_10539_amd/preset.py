@@ -20,7 +20,15 @@ Protocol (Sec. III-C), pure-LBM branch:
 `fork_storage` additionally forks the state after initialisation into a
 second run with another storage form (lbm_get_state / lbm_set_state) and
 takes it through the same evolution, the paper's compare-from-a-common-state
-pattern applied to precision.  The PINN branch is not part of this library.
+pattern applied to precision.
+
+`pinn_beta` adds the PINN-LBM branch of the protocol, forked from the same
+initialised state: before each evolution segment the network of Sec. III-B
+is trained (PyTorch, learning rate 3e-4) on the branch's current state for
+300, 240, 180, 120 and 60 epochs (the "decreasing training epochs" of
+Sec. III-C), and the state is corrected at its interface cells on the GPU
+(lbm_pinn_correct, blending factor pinn_beta); its final metrics fill the
+second column of Tables I and II.
 
     python -m paper_2504_10539_amd.preset --nx 256 --segment 500
 """
@@ -52,8 +60,24 @@ def _evolve(sim, segment: int, every: int) -> tuple[list, list]:
     return series, ends
 
 
+PINN_EPOCHS = (300, 240, 180, 120, 60)
+
+
+def _evolve_pinn(sim, segment: int, every: int, beta: float, seed: int) -> tuple[list, list]:
+    from . import pinn
+    net = pinn.make_net(seed=seed, device=sim.device)
+    series, ends = [], []
+    for ep in PINN_EPOCHS:
+        pinn.train(net, pinn.state_fields(sim), G_PAPER, TAU_PAPER, epochs=ep, seed=seed)
+        sim.pinn_correct(pinn.pack(net), beta)
+        series += [_brief(m) for m in sim.step_series(segment, every)]
+        ends.append(_brief(sim.metrics()))
+    return series, ends
+
+
 def run(nx: int = 256, segment: int = 500, every: int = 10, storage: int = None,
-        rho0: float = 1.0, seed: int = 1, fork_storage: int | None = None) -> dict:
+        rho0: float = 1.0, seed: int = 1, fork_storage: int | None = None,
+        pinn_beta: float | None = None) -> dict:
     """Runs the protocol; returns the series, the segment ends and the tables."""
     storage = lbm.LBM_F32 if storage is None else storage
     drops = inputs.single_droplet(nx, nx / 6.0)
@@ -67,6 +91,10 @@ def run(nx: int = 256, segment: int = 500, every: int = 10, storage: int = None,
     if fork_storage is not None:
         fork = lbm.Simulation(nx, nx, G_PAPER, TAU_PAPER, fork_storage, rho0)
         fork.set_state(sim.get_state())
+    coupled = None
+    if pinn_beta is not None:
+        coupled = lbm.Simulation(nx, nx, G_PAPER, TAU_PAPER, storage, rho0)
+        coupled.set_state(sim.get_state())
     out["evolution_series"], out["segment_ends"] = _evolve(sim, segment, every)
     final = out["segment_ends"][-1]
     out["table_I"] = {k: final[k] for k in TABLE_I}
@@ -77,6 +105,12 @@ def run(nx: int = 256, segment: int = 500, every: int = 10, storage: int = None,
                        "table_I": {k: ends[-1][k] for k in TABLE_I},
                        "table_II": {k: ends[-1][k] for k in TABLE_II}}
         fork.close()
+    if coupled is not None:
+        series, ends = _evolve_pinn(coupled, segment, every, pinn_beta, seed)
+        out["pinn"] = {"beta": pinn_beta, "epochs": list(PINN_EPOCHS), "segment_ends": ends,
+                       "table_I": {k: ends[-1][k] for k in TABLE_I},
+                       "table_II": {k: ends[-1][k] for k in TABLE_II}}
+        coupled.close()
     sim.close()
     return out
 
@@ -90,9 +124,11 @@ def main() -> None:
     ap.add_argument("--fork-fp16", action="store_true",
                     help="also fork the initialised state into FP16-shifted storage")
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--pinn-beta", type=float, default=None,
+                    help="also run the PINN-LBM branch with this blending factor")
     a = ap.parse_args()
     r = run(a.nx, a.segment, a.every, lbm.LBM_F16_SHIFTED if a.fp16 else lbm.LBM_F32, seed=a.seed,
-            fork_storage=lbm.LBM_F16_SHIFTED if a.fork_fp16 else None)
+            fork_storage=lbm.LBM_F16_SHIFTED if a.fork_fp16 else None, pinn_beta=a.pinn_beta)
     print(json.dumps(r))
 
 

@@ -48,3 +48,20 @@ def test_paper_protocol_matches_oracle(nthreads):
     for k in ("W_eff", "E_int"):
         assert r["fork"]["table_II"][k] == pytest.approx(final[k], rel=0.02)
     assert np.isfinite([m["mass"] for m in r["evolution_series"]]).all()
+
+
+def test_paper_protocol_with_the_pinn_branch():
+    """The PINN-LBM branch of the protocol (Sec. III-C) forks from the same
+    initialised state, trains and corrects before each of the five segments,
+    and reports both columns of Tables I and II."""
+    from paper_2504_10539_amd import preset
+    r = preset.run(nx=48, segment=40, every=20, pinn_beta=0.5)
+    assert len(r["pinn"]["segment_ends"]) == 5
+    assert all(m["finite"] == 1 for m in r["pinn"]["segment_ends"])
+    # the fork is a new run whose step count starts at the fork
+    assert r["pinn"]["segment_ends"][-1]["step"] == 5 * 40
+    assert r["segment_ends"][-1]["step"] == 500 + 5 * 40
+    for k in ("W", "Gmax", "drho"):
+        assert np.isfinite(r["pinn"]["table_I"][k])
+    # the corrections changed the run
+    assert r["pinn"]["table_II"]["E_int"] != r["table_II"]["E_int"]

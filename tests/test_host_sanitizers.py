@@ -39,7 +39,7 @@ def _run(cmd, **kw):
 def _build(kind, out):
     san = SANITIZERS[kind]
     jobs = []
-    for src in ("sc_kernels.hip", "sc_noalloc.hip"):
+    for src in ("sc_kernels.hip", "sc_noalloc.hip", "sc_pinn.hip"):
         jobs.append([HIPCC, "-x", "hip", "--offload-new-driver", "--cuda-host-only", *COMMON, *san,
                      "-c", os.path.join(CSRC, src), "-o", os.path.join(out, src + ".o")])
     for src in ("sc_runtime.cpp", "sc_server.cpp"):
