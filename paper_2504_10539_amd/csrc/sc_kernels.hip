@@ -1091,8 +1091,10 @@ __device__ __forceinline__ void ring_force(const float* dn, const float* md, con
   force_of(md[t], md[r], up[t], md[l], dn[t], up[r], up[l], dn[l], dn[r], G, Fx, Fy);
 }
 
-// Ring slot of march row r >= -9 (three rows of each ring are live at a time).
+// Ring slot of march row r >= -9 in a ring of three rows, and of row r >= -10
+// in a ring of two.
 __device__ __forceinline__ int slot3(int r) { return (r + 9) % 3; }
+__device__ __forceinline__ int slot2(int r) { return (r + 10) & 1; }
 
 // Calls fn(integral_constant<int, I>) for I = 0, 1, ... in order.
 template <class Fn, int... I>
@@ -1129,9 +1131,19 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
                         : (NR % 2 == 0 ? NR : 2 * NR);
   constexpr bool kFixedRing = U % 3 == 0;
   constexpr int NF = kInPlace ? NR : 2;  // FP32 rows of the first step
-  __shared__ float psa[3][NT];    // psi(t) rows
-  __shared__ float fs[3][9][NT];  // f*(t + 1) rows, as read back from storage
-  __shared__ float psb[3][NT];    // psi(t + 1) rows
+  __shared__ float psa[3][NT];  // psi(t) rows
+  __shared__ float psb[3][NT];  // psi(t + 1) rows
+  // f*(t + 1) of the rows that the pull of row j + 1 reads, as read back from
+  // storage, each population kept only until it is read.  Populations 0, 1
+  // and 3 come from row j + 1 itself, written one position earlier (two
+  // slots).  Of the rows on either side, the one written at this position
+  // (row j + 2) is read at once (one slot) and the one written two positions
+  // earlier (row j) is read last (three slots); which three populations each
+  // side supplies follows the march direction.  18 rows of NT values instead
+  // of 27, which lets more workgroups share a CU's LDS.
+  __shared__ float fmd[2][3][NT];   // populations 0, 1, 3
+  __shared__ float fnew[3][NT];     // row j + 2: the side it lies on
+  __shared__ float fold[3][3][NT];  // row j: the other side
   __shared__ double rr[DIAG ? 3 : 1][DIAG ? NT : 1];  // FP64 rho(t) rows
   const int nitems = *nitems_p;
   const int t = strip_slot<S, NT>();  // LDS ring index
@@ -1195,6 +1207,7 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         constexpr int kd = (u + 3) % NR;  // slot of row j + 3
         // ring slot of row j + d (j = u mod U)
         auto ring = [&](int d) { return kFixedRing ? (u + d + 9) % 3 : slot3(j + d); };
+        auto ring2 = [&](int d) { return kFixedRing ? (u + d + 10) % 2 : slot2(j + d); };
         float(&fa_c)[10] = fa[kInPlace ? kd : (u + 3) & 1];
         float(&fa_p)[10] = fa[kInPlace ? (u + 2) % NR : (u + 2) & 1];
         float(&fb_c)[10] = fb[(u + 1) & 1];
@@ -1217,24 +1230,43 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
                      Fy);
           const float rho = fa_p[9];
           collide(fa_p, rho, Fx, Fy, s.tau, s.omega);
+          float g[9];
 #pragma unroll
-          for (int i = 0; i < 9; ++i) fs[ring(2)][i][t] = s.through_storage(fa_p[i], i, rho);
+          for (int i = 0; i < 9; ++i) g[i] = s.through_storage(fa_p[i], i, rho);
+          // Row j + 2 is the row below row j + 1 (populations 2, 5, 6 are
+          // pulled from it) when marching upwards, the row above it
+          // (populations 4, 7, 8) when marching downwards.
+          float(*md)[NT] = fmd[ring2(2)];
+          float(*old)[NT] = fold[ring(2)];
+          float(*dn)[NT] = upward ? fnew : old;
+          float(*up)[NT] = upward ? old : fnew;
+          md[0][t] = g[0];
+          md[1][t] = g[1];
+          md[2][t] = g[3];
+          dn[0][t] = g[2];
+          dn[1][t] = g[5];
+          dn[2][t] = g[6];
+          up[0][t] = g[4];
+          up[1][t] = g[7];
+          up[2][t] = g[8];
         }
         __syncthreads();
         if ((!kLead || j >= -2) && stage_b) {
           // row j + 1: f_i(x) = f*_i(x - e_i), rows below feed e_iy = +1
-          const float(*dn)[NT] = fs[ring(1 + below)];
-          const float(*md)[NT] = fs[ring(1)];
-          const float(*up)[NT] = fs[ring(1 - below)];
+          // (row j is the one written two positions ago)
+          const float(*md)[NT] = fmd[ring2(1)];
+          const float(*old)[NT] = fold[ring(0)];
+          const float(*dn)[NT] = upward ? fnew : old;
+          const float(*up)[NT] = upward ? old : fnew;
           fb_c[0] = md[0][t];
           fb_c[1] = md[1][tl];
-          fb_c[2] = dn[2][t];
-          fb_c[3] = md[3][tr];
-          fb_c[4] = up[4][t];
-          fb_c[5] = dn[5][tl];
-          fb_c[6] = dn[6][tr];
-          fb_c[7] = up[7][tr];
-          fb_c[8] = up[8][tl];
+          fb_c[2] = dn[0][t];
+          fb_c[3] = md[2][tr];
+          fb_c[4] = up[0][t];
+          fb_c[5] = dn[1][tl];
+          fb_c[6] = dn[2][tr];
+          fb_c[7] = up[1][tr];
+          fb_c[8] = up[2][tl];
           fb_c[9] = density(fb_c);
           psb[ring(1)][t] = psi_of(fb_c[9]);
         }
