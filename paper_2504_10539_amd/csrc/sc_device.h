@@ -207,8 +207,33 @@ __device__ __forceinline__ float density(const float f[9]) {
   return r;
 }
 
-// Pseudopotential psi(rho) = 1 - exp(-rho).
-__device__ __forceinline__ float psi_of(float rho) { return 1.0f - expf(-rho); }
+// Pseudopotential psi(rho) = 1 - exp(-rho).  exp(-rho) = 2^(p + d) with
+// p = fl(-rho L), L = log2(e) rounded to FP32, and d the rest of -rho log2(e):
+// the exact residual of that product (one FMA) plus -rho times the part of
+// log2(e) beyond L.  2^p comes from the hardware base-2 exponential
+// (v_exp_f32) and d enters to first order, 2^(p + d) = 2^p (1 + d ln 2) up to
+// a relative (d ln 2)^2 / 2 < 1e-14.  Seven instructions where the library
+// exp takes thirteen (its range reduction guards arguments far outside what a
+// density reaches).
+__device__ __forceinline__ float psi_of(float rho) {
+  constexpr float kLog2e = 1.44269502f;      // fl(log2 e)
+  constexpr float kLog2eLo = 1.92596299e-8f;  // log2 e - fl(log2 e)
+  constexpr float kLn2 = 0.693147182f;
+  const float p = -rho * kLog2e;
+  const float d = fmaf(-rho, kLog2eLo, fmaf(-rho, kLog2e, -p));
+  const float e = __builtin_amdgcn_exp2f(p);
+  return 1.0f - fmaf(e, d * kLn2, e);
+}
+
+// 1.0f that the compiler cannot see through: h * one + s then keeps its FMA
+// form, with h widened from half precision, and is selected as one
+// mixed-precision FMA (v_fma_mix_f32) instead of a conversion and an add.
+// The product is exact, so the result equals float(h) + s.
+__device__ __forceinline__ float opaque_one() {
+  float r = 1.0f;
+  asm("" : "+s"(r));
+  return r;
+}
 
 // Interaction force F = -G psi(x) sum_i w_i psi(x + e_i) e_i.  The stencil
 // sum is taken as differences of opposite neighbours first: neighbouring psi

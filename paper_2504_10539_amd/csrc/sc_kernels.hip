@@ -913,6 +913,7 @@ struct Fused2 {
   uint64_t src, dst;    // population arrays read and written
   uint64_t qsrc, qdst;  // their reference-density planes (per-cell shift)
   float sh[9];
+  float one;  // 1.0, opaque to the compiler (opaque_one)
   int nx, ny, y0, h, dir, wcols;
   uint32_t lrow, prow;  // bytes of a lattice row (nine population rows) and of one population row
   uint32_t bc, bm, bp;  // byte offsets of this thread's column and its neighbours
@@ -965,6 +966,7 @@ struct Fused2 {
     const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
 #pragma unroll
     for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
+    one = opaque_one();
     const int t = strip_slot<S, NT>();
     int c = (ti.x0 - 3 + t) % nx;
     c = c < 0 ? c + nx : c;
@@ -1021,11 +1023,11 @@ struct Fused2 {
     }
   }
 
-  // Widening of the pulled values, as the storage type reads them back.  For
-  // per-cell-shift storage one mixed-precision FMA per value (rhohat * w_i + h,
-  // both halves read directly), equal to StoreF16C::decode.  (The same form
-  // for the FP16-shifted values, float(h) + w_i rho0, is also exact, but the
-  // compiler then needs some 35 more VGPRs for that kernel.)
+  // Widening of the pulled values, as the storage type reads them back: one
+  // mixed-precision FMA per value.  Per-cell-shift storage: rhohat * w_i + h,
+  // both halves read directly, equal to StoreF16C::decode.  FP16-shifted:
+  // h * 1 + w_i rho0, equal to StoreF16S::load (the 1 is opaque to the
+  // compiler, which otherwise turns the FMA into a conversion and an add).
   __device__ __forceinline__ void decode(const RawCell<S>& r, float (&f)[10]) const {
     const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
 #pragma unroll
@@ -1033,9 +1035,14 @@ struct Fused2 {
       if constexpr (S::kCellShift)
         f[i] = mix_lo(r.q[i], ws[i], r.v[i]);
       else
-        f[i] = S::load(&r.v[i], sh[i]);
+        f[i] = widen(r.v[i], sh[i]);
     }
     f[9] = density(f);
+  }
+
+  // An FP16-shifted value read back: float(h) + shift in one mixed FMA.
+  __device__ __forceinline__ float widen(T h, float shift) const {
+    return fmaf(static_cast<float>(h), one, shift);
   }
 
   // A post-collision value as the next step would read it back from storage.
@@ -1045,8 +1052,7 @@ struct Fused2 {
       const T rh = S::ref(rho);
       return mix_lo(rh, ws[i], S::encode(v, rh, ws[i]));
     } else if constexpr (sizeof(T) == 2) {
-      const T hv = S::pack(v, sh[i]);
-      return S::load(&hv, sh[i]);
+      return widen(S::pack(v, sh[i]), sh[i]);
     } else {
       return v;  // FP32 stores the value itself
     }
@@ -1124,9 +1130,9 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
   constexpr bool kInPlace = std::is_same<S, StoreF32>::value;
   constexpr int NR = kInPlace ? PF + 2 : PF + 1;
   // With U a multiple of 3 the LDS ring slots are constants too (not taken
-  // for per-cell-shift storage and the diagnostics variant, whose longer
-  // period needs too many registers).
-  constexpr int U = !DIAG && ((NR == 2 && !S::kCellShift) || NR == 3)
+  // for the diagnostics variant, whose longer period needs too many
+  // registers).
+  constexpr int U = !DIAG && (NR == 2 || NR == 3)
                         ? 6
                         : (NR % 2 == 0 ? NR : 2 * NR);
   constexpr bool kFixedRing = U % 3 == 0;
@@ -1318,8 +1324,17 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
 // W output columns per workgroup (at most NT - kFusedHalo): with W a
 // multiple of 16, every strip of an FP32 row starts and ends on a 64-byte
 // boundary, so no write granule is shared by two workgroups.
+//
+// Per-cell-shift storage with one row of loads in flight is compiled for at
+// least four wavefronts per SIMD: it fits in 128 VGPRs without spilling
+// (unbounded, the compiler takes 133 and the CU holds three).
+template <class S, int PF>
+constexpr int step2_min_waves() {
+  return S::kCellShift && PF == 1 ? 4 : 1;
+}
 template <class S, int NT, int PF, int W>
-__global__ __launch_bounds__(NT) void k_step2(const InstDesc* __restrict__ descs,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(step2_min_waves<S, PF>())))
+void k_step2(const InstDesc* __restrict__ descs,
                                               const TileItem* __restrict__ items,
                                               const int* __restrict__ nitems_p, int sub) {
   two_step_march<S, NT, PF, W, false>(descs, items, nitems_p, sub, nullptr);
