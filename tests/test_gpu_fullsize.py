@@ -25,7 +25,9 @@ def _gpu():
     need_gpu()
 
 
-def _windows(sim_state, n, drops, G, tau, seed, count, rng_seed, rho0=None):
+def _windows(sim_state, n, drops, G, tau, seed, count, rng_seed, rho0=None, absolute=False):
+    """max |f_gpu - f_oracle| over each window's valid cells, relative to the
+    window's max |f_oracle| (absolute=True: not divided)."""
     rng = np.random.default_rng(rng_seed)
     errs = []
     for _ in range(count):
@@ -33,7 +35,7 @@ def _windows(sim_state, n, drops, G, tau, seed, count, rng_seed, rho0=None):
         f0 = oracle.droplet_state(WIN, WIN, drops, seed=seed, period=(n, n), origin=(ox, oy))
         ref = oracle.step(f0, G, tau, K, 8)[:, LO:HI, LO:HI]
         got = to_np(sim_state[:, oy + LO:oy + HI, ox + LO:ox + HI])
-        errs.append(float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+        errs.append(float(np.max(np.abs(got - ref)) / (1.0 if absolute else np.max(np.abs(ref)))))
     return errs
 
 
@@ -59,9 +61,13 @@ def test_many_droplets_4096_fp16_windows():
     drops = inputs.many_droplets(n, 2000, 8, 48, seed=3)
     sim = lbm().Simulation(n, n, G, tau, lbm().LBM_F16_SHIFTED, 0.5).init_droplets(drops, seed=3)
     sim.step(K)
-    errs = _windows(sim.get_state(), n, drops, G, tau, 3, 3, 12)
-    print("4096 fp16 window errors", errs)
-    assert max(errs) < 2e-3
+    errs = _windows(sim.get_state(), n, drops, G, tau, 3, 3, 12, absolute=True)
+    print("4096 fp16 window errors (absolute)", errs)
+    # Each step rounds every stored value once to half precision: at most half
+    # an ulp of |f_i - w_i rho0| < 1, i.e. 2^-12.  K steps carry at most K such
+    # roundings (the one-step bound is asserted in test_gpu_fp16.py); an error
+    # in the step itself would be far larger.
+    assert max(errs) < K * 2.0 ** -12
 
 
 def test_many_droplets_4096_fp16_cell_windows():
