@@ -44,6 +44,17 @@ constexpr double kInterface = 0.01;  // Eq. (9) threshold on |grad rho|
 typedef _Float16 half4 __attribute__((ext_vector_type(4)));
 typedef float float4v __attribute__((ext_vector_type(4)));
 
+// tanh(z) = 1 - 2 / (exp(2 z) + 1) from the hardware base-2 exponential and
+// reciprocal: five instructions where the library tanhf takes some thirty.
+// The form holds for either sign (exp(2 z) = inf gives 1, exp(2 z) = 0 gives
+// -1).  Its absolute error stays below 4e-7 (every float z with
+// 2^-30 <= |z| <= 20 checked against FP64 tanh), far below the
+// half-precision rounding of the activation that follows.
+__device__ __forceinline__ float tanh_fast(float z) {
+  const float e = __builtin_amdgcn_exp2f(z * 2.88539004f);  // 2 log2(e)
+  return fmaf(-2.0f, __builtin_amdgcn_rcpf(e + 1.0f), 1.0f);
+}
+
 // One 16 x 16 x 16 matrix multiply-add on the matrix cores.  Lane l holds
 // A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16] (j = 0..3, one half
 // each) and D[4 (l / 16) + j][l % 16] (one float each).
@@ -51,8 +62,8 @@ __device__ __forceinline__ float4v mfma16(half4 a, half4 b, float4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
 }
 
-// B fragments of one layer for the wavefront's output features: feature
-// n = col0 + 16 cb + (lane % 16), inputs k = 16 s + 4 (lane / 16) + j, from
+// A fragments of one layer for the wavefront's output features: feature
+// m = col0 + 16 cb + (lane % 16), inputs k = 16 s + 4 (lane / 16) + j, from
 // W (out x in, FP32) rounded to half.
 template <int KS, int NCB>
 __device__ __forceinline__ void load_weights(const float* __restrict__ W, int in, int col0,
@@ -67,31 +78,37 @@ __device__ __forceinline__ void load_weights(const float* __restrict__ W, int in
         w[cb][s][j] = static_cast<_Float16>(W[(size_t)(col0 + 16 * cb + nl) * in + 16 * s + kq + j]);
 }
 
-// One hidden layer over the tile's 64 cells: out = tanh(in W^T + b) for the
+// One hidden layer over the tile's 64 cells: out = tanh(W in + b) for the
 // wavefront's features col0 .. col0 + 16 NCB - 1, with KS blocks of 16 inputs.
+// The weights are the A operand and the activations (cells as columns) the B
+// operand, so each lane's four results are four consecutive features of one
+// cell: they go to LDS as one 8-byte write, and the accumulators start from
+// the biases.
 template <int KS, int NCB>
 __device__ __forceinline__ void dense_tanh(const _Float16 (*in)[kStride], _Float16 (*out)[kStride],
                                            const half4 (&w)[NCB][KS], const float* bias, int col0,
                                            int lane) {
   const int r16 = lane & 15, kq = 4 * (lane >> 4);
+  float4v b[NCB];
+#pragma unroll
+  for (int cb = 0; cb < NCB; ++cb) b[cb] = *reinterpret_cast<const float4v*>(&bias[col0 + 16 * cb + kq]);
 #pragma unroll
   for (int rb = 0; rb < kTile / 16; ++rb) {
     float4v acc[NCB];
 #pragma unroll
-    for (int cb = 0; cb < NCB; ++cb) acc[cb] = float4v{0.f, 0.f, 0.f, 0.f};
+    for (int cb = 0; cb < NCB; ++cb) acc[cb] = b[cb];
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       const half4 a = *reinterpret_cast<const half4*>(&in[rb * 16 + r16][16 * s + kq]);
 #pragma unroll
-      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma16(a, w[cb][s], acc[cb]);
+      for (int cb = 0; cb < NCB; ++cb) acc[cb] = mfma16(w[cb][s], a, acc[cb]);
     }
 #pragma unroll
     for (int cb = 0; cb < NCB; ++cb) {
-      const int col = col0 + 16 * cb + r16;
-      const float b = bias[col];
+      half4 h;
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        out[rb * 16 + kq + j][col] = static_cast<_Float16>(tanhf(acc[cb][j] + b));
+      for (int j = 0; j < 4; ++j) h[j] = static_cast<_Float16>(tanh_fast(acc[cb][j]));
+      *reinterpret_cast<half4*>(&out[rb * 16 + r16][col0 + 16 * cb + kq]) = h;
     }
   }
 }
@@ -126,8 +143,10 @@ struct PinnArgs {
 template <class S, bool CORRECT>
 __global__ __launch_bounds__(kThreads) void k_pinn(PinnArgs a) {
   using T = typename S::T;
-  __shared__ _Float16 act[2][kTile][kStride];
-  __shared__ float sw1[kH1][2], sb1[kH1], sb2[kH2], sb3[kH3], sb4[kH4], sw5[kOut][kH4], sb5[kOut];
+  __shared__ __attribute__((aligned(16))) _Float16 act[2][kTile][kStride];
+  __shared__ float part[kThreads / 64][kOut][kTile];  // layer-5 partial sums per wavefront
+  __shared__ float sw1[kH1][2], sb1[kH1], sw5[kOut][kH4], sb5[kOut];
+  __shared__ __attribute__((aligned(16))) float sb2[kH2], sb3[kH3], sb4[kH4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float* P = a.params;
   for (int i = threadIdx.x; i < kH1; i += kThreads) {
@@ -174,12 +193,17 @@ __global__ __launch_bounds__(kThreads) void k_pinn(PinnArgs a) {
     {
       const float xh = (float)(2 * x + 1) / (float)nx - 1.0f;
       const float yh = (float)(2 * y + 1) / (float)ny - 1.0f;
+      typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+      half8 h[2];
 #pragma unroll
       for (int f = 0; f < 16; ++f) {
         const int n = 16 * wave + f;
         const float z = fmaf(sw1[n][0], xh, fmaf(sw1[n][1], yh, sb1[n]));
-        act[0][lane][n] = static_cast<_Float16>(tanhf(z));
+        h[f / 8][f % 8] = static_cast<_Float16>(tanh_fast(z));
       }
+      half8* dst = reinterpret_cast<half8*>(&act[0][lane][16 * wave]);
+      dst[0] = h[0];
+      dst[1] = h[1];
     }
     __syncthreads();
     dense_tanh(act[0], act[1], w2, sb2, 32 * wave, lane);
@@ -188,15 +212,29 @@ __global__ __launch_bounds__(kThreads) void k_pinn(PinnArgs a) {
     __syncthreads();
     dense_tanh(act[0], act[1], w4, sb4, 16 * wave, lane);
     __syncthreads();
-    if (wave == 0) {
-      // layer 5 (FP32, linear): the lane's cell
-      float o[kOut] = {sb5[0], sb5[1], sb5[2]};
-#pragma unroll 8
-      for (int j = 0; j < kH4; ++j) {
-        const float h = static_cast<float>(act[1][lane][j]);
+    {
+      // layer 5 (FP32, linear), split over the wavefronts: wavefront w sums
+      // inputs 16 w .. 16 w + 15 of the lane's cell (two 16-byte LDS reads)
+      typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+      const half8* src = reinterpret_cast<const half8*>(&act[1][lane][16 * wave]);
+      const half8 h0 = src[0], h1 = src[1];
+      float q[kOut] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int k = 0; k < kOut; ++k) o[k] = fmaf(sw5[k][j], h, o[k]);
+      for (int j = 0; j < 16; ++j) {
+        const float h = static_cast<float>(j < 8 ? h0[j] : h1[j - 8]);
+#pragma unroll
+        for (int k = 0; k < kOut; ++k) q[k] = fmaf(sw5[k][16 * wave + j], h, q[k]);
       }
+#pragma unroll
+      for (int k = 0; k < kOut; ++k) part[wave][k][lane] = q[k];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      // the lane's cell: bias plus the four partial sums in wavefront order
+      float o[kOut];
+#pragma unroll
+      for (int k = 0; k < kOut; ++k)
+        o[k] = sb5[k] + ((part[0][k][lane] + part[1][k][lane]) + (part[2][k][lane] + part[3][k][lane]));
       if constexpr (!CORRECT) {
         if (live) {
           const size_t c = (size_t)y * nx + x;
@@ -243,9 +281,15 @@ __global__ __launch_bounds__(256) void k_rho64(const typename S::T* __restrict__
   }
 }
 
-int pinn_grid(int nx, int ny) {
+// One workgroup per resident slot (the kernel loops over tiles), so that
+// every workgroup starts at once and the tiles divide evenly among them.
+int pinn_grid(const void* fn, int nx, int ny) {
   const long tiles = (long)((nx + kTile - 1) / kTile) * ny;
-  return (int)std::min<long>(tiles, 4L * device_cu_count());
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return (int)std::max<long>(1, std::min<long>(tiles, (long)per_cu * device_cu_count()));
 }
 
 template <bool CORRECT, class F>
@@ -277,8 +321,9 @@ lbm_status lbm_pinn_infer(lbm_ctx* c, const float* params, float* rho, float* ux
     a.out[2] = uy;
     a.nx = c->p.nx;
     a.ny = c->p.ny;
-    hipLaunchKernelGGL((k_pinn<StoreF32, false>), dim3(pinn_grid(a.nx, a.ny)), dim3(kThreads), 0,
-                       c->stream, a);
+    const void* fn = reinterpret_cast<const void*>(&k_pinn<StoreF32, false>);
+    hipLaunchKernelGGL((k_pinn<StoreF32, false>), dim3(pinn_grid(fn, a.nx, a.ny)), dim3(kThreads),
+                       0, c->stream, a);
     SCLBM_HIP(hipGetLastError());
     return LBM_OK;
   });
@@ -311,7 +356,8 @@ lbm_status lbm_pinn_correct(lbm_ctx* c, const float* params, double beta, uint8_
       using S = decltype(tag);
       hipLaunchKernelGGL(k_rho64<S>, dim3(g), dim3(256), 0, c->stream,
                          reinterpret_cast<const typename S::T*>(a.pop), a.nx, a.ny, a.rho0, rho64);
-      hipLaunchKernelGGL((k_pinn<S, true>), dim3(pinn_grid(a.nx, a.ny)), dim3(kThreads), 0,
+      const void* fn = reinterpret_cast<const void*>(&k_pinn<S, true>);
+      hipLaunchKernelGGL((k_pinn<S, true>), dim3(pinn_grid(fn, a.nx, a.ny)), dim3(kThreads), 0,
                          c->stream, a);
       return hipGetLastError();
     });
