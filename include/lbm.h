@@ -59,8 +59,8 @@ typedef int32_t lbm_status;
                               read back as float(h_i) + w_i rho0; 18 bytes per
                               cell per buffer; arithmetic stays FP32 */
 #define LBM_F16_CELL 2     /* FP16 shifted per cell: the nine values a cell x
-                              stores hold A_i(x) - w_i rhohat(x) (the FP32
-                              difference rounded once to nearest even), with
+                              stores hold A_i(x) - w_i rhohat(x) (rounded
+                              once to nearest even from the exact value), with
                               rhohat(x) = half(rho) of that cell stored in a
                               tenth FP16 plane; read back as rhohat w_i + h_i
                               rounded once.  20 bytes per cell per buffer, 40
@@ -69,14 +69,17 @@ typedef int32_t lbm_status;
                               the record of the nine values A_i(x) it wrote -
                               its density rho (the record's mass) and the
                               momentum jx, jy of the A_i in FP32, and A_3 .. A_8
-                              as h_i = half(A_i - w_i rho) (RNE) - read back as
+                              as h_i = half(A_i - w_i rho) (rounded once from
+                              the exact value) - read back as
                               A_i = rho w_i + h_i (i >= 3), A_1 and A_2 from the
                               momentum, A_0 = rho - (the other eight).  Mass and
                               momentum pass between cells at FP32 rounding;
                               only non-conserved moments round to half
                               precision.  24 bytes per cell per buffer, 48
-                              bytes moved per lattice update.  Strip tile
-                              shapes only (steps = 1, paired = 0) */
+                              bytes moved per lattice update (24 with two
+                              steps per launch).  Tile shapes: strips, and
+                              two-step shapes of width <= threads - 8 (no
+                              paired-column shapes) */
 
 typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;

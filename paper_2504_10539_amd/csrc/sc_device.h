@@ -105,6 +105,19 @@ __host__ __device__ __forceinline__ uint64_t rhat_row(int y, int nx, int ny) {
 
 // ------------------------------------------------------------------ storage
 
+// half(v - w r) rounded once from the exact value (ties to even): one
+// mixed-precision FMA with a half-precision result (v_fma_mixlo_f16), w
+// uniform across the wavefront.  Written out rather than left to the
+// compiler, which fuses a half conversion of an FMA into this instruction
+// only where both sit in one basic block: elsewhere the difference is
+// rounded twice, and two kernels could then store different halves for the
+// same value.
+__device__ __forceinline__ _Float16 half_of_fma(float v, float w, float r) {
+  uint32_t o;
+  asm("v_fma_mixlo_f16 %0, -%1, %2, %3" : "=v"(o) : "s"(w), "v"(r), "v"(v));
+  return __builtin_bit_cast(_Float16, (uint16_t)o);
+}
+
 // FP32 populations.  Stores stream past the caches (the buffer written is
 // read again only by the next step).
 struct StoreF32 {
@@ -135,7 +148,8 @@ struct StoreF16S {
 };
 
 // FP16 populations shifted per cell: the nine values a cell stores hold
-// f_i - w_i rhohat, where rhohat = half(rho) of that (writing) cell and is
+// half(f_i - w_i rhohat) (rounded once), where rhohat = half(rho) of that
+// (writing) cell and is
 // stored beside them (rhat_row).  Read back as rhohat * w_i + h, rounded
 // once.  Only the non-equilibrium and velocity parts of f_i are left to round
 // to half precision, in either phase.
@@ -148,6 +162,11 @@ struct StoreF16C {
   __device__ static __forceinline__ float decode(T h, T rh, float w) {
     return __builtin_fmaf(static_cast<float>(rh), w, static_cast<float>(h));
   }
+  // half(v - w rhohat): the compiler fuses the conversion into the FMA
+  // (v_fma_mixlo_f16, one rounding) in every kernel that stores this form;
+  // written as half_of_fma it costs the four-wave two-step kernel a spilled
+  // register.  The tile-shape tests check that every kernel stores the same
+  // halves.
   __device__ static __forceinline__ T encode(float v, T rh, float w) {
     return static_cast<T>(__builtin_fmaf(-w, static_cast<float>(rh), v));
   }
@@ -157,7 +176,7 @@ struct StoreF16C {
 // FP16 populations with exact conserved moments.  A cell x keeps a record of
 // the nine values A_i(x) it wrote: its density rho (the mass of the record)
 // and the momentum jx, jy of the A_i in FP32, and A_3 .. A_8 as
-// h_i = half(A_i - w_i rho) (round to nearest even).  A_1 and A_2 are rebuilt
+// h_i = half(A_i - w_i rho) (rounded once, half_of_fma).  A_1 and A_2 are rebuilt
 // from the momentum and A_0 from the mass (mom_decode), so the mass and
 // momentum a cell hands on to its neighbours are exact up to FP32 rounding and
 // only non-conserved moments round to half precision; the BGK collision
@@ -306,12 +325,12 @@ __device__ __forceinline__ void mom_decode(float rho, float jx, float jy, const 
 __device__ __forceinline__ void mom_encode(const float* v, float rho, float& jx, float& jy,
                                            _Float16 (&h)[6]) {
   momentum(v, jx, jy);
-  h[0] = static_cast<_Float16>(__builtin_fmaf(-kW1, rho, v[3]));
-  h[1] = static_cast<_Float16>(__builtin_fmaf(-kW1, rho, v[4]));
-  h[2] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[5]));
-  h[3] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[6]));
-  h[4] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[7]));
-  h[5] = static_cast<_Float16>(__builtin_fmaf(-kW2, rho, v[8]));
+  h[0] = half_of_fma(v[3], kW1, rho);
+  h[1] = half_of_fma(v[4], kW1, rho);
+  h[2] = half_of_fma(v[5], kW2, rho);
+  h[3] = half_of_fma(v[6], kW2, rho);
+  h[4] = half_of_fma(v[7], kW2, rho);
+  h[5] = half_of_fma(v[8], kW2, rho);
 }
 
 // 1 / x from the hardware reciprocal (within 1 ulp) and one FMA correction

@@ -883,12 +883,31 @@ __global__ __launch_bounds__(64 * NW) void k_step_pair(const InstDesc* __restric
 // One barrier separates each stage from the next.  The band's rows are
 // reached through three halo rows above and below; a strip writes W <= NT - 6
 // columns.
+//
+// Moment storage keeps a record per cell (the values it wrote, as mass,
+// momentum and six half-precision deviations), so stage 1 is split in two:
+// each thread loads and decodes the record of its own column of row j + 4
+// into a fourth LDS ring, and after a barrier pulls f(t) of row j + 3 from
+// that ring.  The pull costs one more halo column per side (slot k holds
+// column x0 - 4 + k, W <= NT - 8) and one more halo row above and below.
 
 template <class S>
 struct RawCell {
   typename S::T v[9];
   typename S::T q[9];  // reference densities (per-cell-shift storage)
 };
+
+// A moment record as loaded: mass, momentum and the six deviations.
+struct RawRec {
+  float r[3];
+  _Float16 h[6];
+};
+
+// Halo columns on each side of a two-step strip.
+template <class S>
+constexpr int fused_halo() {
+  return S::kMoment ? 4 : 3;
+}
 
 // Strip slot of this thread: slot k holds column x0 - 3 + k and is the
 // thread's index in the LDS rings.  In FP32 thread t takes slot t + 3 (mod
@@ -905,7 +924,8 @@ __device__ __forceinline__ int strip_slot() {
 
 template <class S, int NT, int PF, int W>
 struct Fused2 {
-  static_assert(W <= NT - kFusedHalo, "three halo lanes on each side");
+  static constexpr int kH = fused_halo<S>();
+  static_assert(W <= NT - 2 * kH, "kH halo lanes on each side");
   using T = typename S::T;
 
   static_assert(SCLBM_ROW_LAYOUT, "lattice row y keeps its nine population rows together");
@@ -917,6 +937,7 @@ struct Fused2 {
   int nx, ny, y0, h, dir, wcols;
   uint32_t lrow, prow;  // bytes of a lattice row (nine population rows) and of one population row
   uint32_t bc, bm, bp;  // byte offsets of this thread's column and its neighbours
+  uint32_t bc4;         // byte offset of this thread's column in an FP32 row
   bool out;             // this thread stores a cell of the second step
   bool wrap;            // the grid is one periodic strip (nx <= NT)
   float G, tau, omega;
@@ -968,25 +989,44 @@ struct Fused2 {
     for (int i = 0; i < 9; ++i) sh[i] = ws[i] * rho0;
     one = opaque_one();
     const int t = strip_slot<S, NT>();
-    int c = (ti.x0 - 3 + t) % nx;
+    int c = (ti.x0 - kH + t) % nx;
     c = c < 0 ? c + nx : c;
     bc = (uint32_t)c * (uint32_t)sizeof(T);
+    bc4 = (uint32_t)c * 4u;
     bm = (uint32_t)wrap_dec(c, nx) * (uint32_t)sizeof(T);
     bp = (uint32_t)wrap_inc(c, nx) * (uint32_t)sizeof(T);
     // A grid no wider than the workgroup is marched as one periodic strip
-    // (x0 = 0): ring column x < nx holds lattice column (x - 3) mod nx, the
+    // (x0 = 0): ring column x < nx holds lattice column (x - kH) mod nx, the
     // ring's neighbours wrap at nx, and every column is written.
     wrap = nx <= NT;
-    out = wrap ? t < nx : (t >= 3 && t - 3 < wcols);
+    out = wrap ? t < nx : (t >= kH && t - kH < wcols);
   }
 
-  // Lattice row of march position j (any j in [-3, h + 2]).  As y0 + h <= ny
-  // the unwrapped row lies in [-3, ny + 2]: one wrap maps it into the grid
-  // once ny >= 3, and for ny = 1 or 2 the row is its low bits.
+  // Lattice row of march position j (any j in [-kH, h + kH - 1]).  As
+  // y0 + h <= ny the unwrapped row lies in [-kH, ny + kH - 1]: one wrap maps
+  // it into the grid once ny >= kH; below that (ny = 1 or 2 for kH = 3, the
+  // low bits) the remainder.
   __device__ __forceinline__ int row_of(int j) const {
     const int y = dir ? y0 + h - 1 - j : y0 + j;
     const int w = y < 0 ? y + ny : (y >= ny ? y - ny : y);
-    return ny < 3 ? (y & (ny - 1)) : w;
+    if constexpr (kH > 3)
+      return ny < kH ? ((y % ny) + ny) % ny : w;
+    else
+      return ny < 3 ? (y & (ny - 1)) : w;
+  }
+
+  // Moment storage: issues the loads of the record of this thread's column
+  // in row j (mass, momentum, six deviations).
+  __device__ __forceinline__ void fetch_record(int j, RawRec& r) const {
+    const int y = row_of(j);
+    const uint64_t b = src + mom_row(y, nx);
+    const uint32_t c2 = fresh(bc), c4 = fresh(bc4);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      r.r[k] = *reinterpret_cast<gptr<const float>>(
+          reinterpret_cast<gptr<const char>>(uniform(b + mom_f32(k, nx))) + c4);
+#pragma unroll
+    for (int i = 3; i < 9; ++i) r.h[i - 3] = ld(b + mom_f16(i, nx), c2);
   }
 
   // Issues the loads of row j's pulled populations (f_i(x) = A_i(x - e_i))
@@ -1045,6 +1085,16 @@ struct Fused2 {
     return fmaf(static_cast<float>(h), one, shift);
   }
 
+  // Moment storage: the nine values a collided cell's record reads back as
+  // (its mass rho, the momentum of v and the six deviations, decoded).
+  __device__ __forceinline__ static void through_record(const float (&v)[10], float rho,
+                                                        float (&g)[9]) {
+    float jx, jy;
+    _Float16 h[6];
+    mom_encode(v, rho, jx, jy, h);
+    mom_decode(rho, jx, jy, h, g);
+  }
+
   // A post-collision value as the next step would read it back from storage.
   __device__ __forceinline__ float through_storage(float v, int i, float rho) const {
     const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
@@ -1076,7 +1126,24 @@ struct Fused2 {
   __device__ __forceinline__ void store(int j, const float (&f)[10]) const {
     const int y = row_of(j);
     const uint32_t c = out ? fresh(bc) : 0x80000000u;
-    if constexpr (S::kCellShift) {
+    if constexpr (S::kMoment) {
+      // the record: the density the cell collided with (its mass), the
+      // momentum of the collided values and the six deviations
+      float jx, jy;
+      _Float16 hv[6];
+      mom_encode(f, f[9], jx, jy, hv);
+      const uint32_t c4 = out ? fresh(bc4) : 0x80000000u;
+      const uint32_t pitch = 24u * (uint32_t)nx;
+      const float r3[3] = {f[9], jx, jy};
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, r3[k]),
+                                              rows(dst + mom_f32(k, nx), y, pitch, 4u * nx),
+                                              (int)c4, 0, 0);
+#pragma unroll
+      for (int i = 3; i < 9; ++i)
+        put(rows(dst + mom_f16(i, nx), y, pitch, 2u * nx), c, hv[i - 3]);
+    } else if constexpr (S::kCellShift) {
       const float ws[9] = {kW0, kW1, kW1, kW1, kW1, kW2, kW2, kW2, kW2};
       const T rh = S::ref(f[9]);
 #pragma unroll
@@ -1151,13 +1218,23 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
   __shared__ float fnew[3][NT];     // row j + 2: the side it lies on
   __shared__ float fold[3][3][NT];  // row j: the other side
   __shared__ double rr[DIAG ? 3 : 1][DIAG ? NT : 1];  // FP64 rho(t) rows
+  // Moment storage: the decoded records A_i of the rows that the pull of row
+  // j + 3 reads, kept by the same rule as the f*(t + 1) rings (row j + 4 is
+  // the newest, row j + 2 the oldest).
+  constexpr bool kM = S::kMoment;
+  __shared__ float amd[kM ? 2 : 1][3][kM ? NT : 1];   // populations 0, 1, 3
+  __shared__ float anew[3][kM ? NT : 1];              // row j + 4: the side it lies on
+  __shared__ float aold[kM ? 3 : 1][3][kM ? NT : 1];  // row j + 2: the other side
+  constexpr int D = fused_halo<S>();  // the march reads rows -D .. h + D - 1
   const int nitems = *nitems_p;
   const int t = strip_slot<S, NT>();  // LDS ring index
   // Columns each stage is valid for: a strip loses one halo column per side
-  // to every stencil.  Lanes that store nothing still run the last collision
-  // (on clamped ring columns) so that the row's stores need no branch.
-  const bool strip_a = t >= 1 && t <= NT - 2;
-  const bool strip_b = t >= 2 && t <= NT - 3;
+  // to every stencil (moment storage: one more, to the pull of stage 1).
+  // Lanes that store nothing still run the last collision (on clamped ring
+  // columns) so that the row's stores need no branch.
+  constexpr int e = kM ? 1 : 0;
+  const bool strip_a = t >= 1 + e && t <= NT - 2 - e;
+  const bool strip_b = t >= 2 + e && t <= NT - 3 - e;
   const int strip_f = min(max(t, 1), NT - 2);
   const int op[10] = {0, 0, 0, 0, 0, 1, 0, 0, 1, 2};  // sum, max, min
   (void)op;
@@ -1189,28 +1266,37 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
       const int tr = kW ? (t == nx - 1 ? 0 : min(t + 1, NT - 1)) : t + 1;
       const int tf = kW ? t : strip_f;
       const int tfl = kW ? tl : tf - 1, tfr = kW ? tr : tf + 1;
-      RawCell<S> raw[kInPlace ? 1 : NR];
+      // (moment storage) ring neighbours of the stage-1 pull, clamped into
+      // the ring for the edge lanes, whose pull is not used
+      const int tal = kW ? tl : max(t - 1, 0), tar = kW ? tr : min(t + 1, NT - 1);
+      using Raw = std::conditional_t<kM, RawRec, RawCell<S>>;
+      Raw raw[kInPlace ? 1 : NR];
       float fa[NF][10], fb[2][10];
-      // Row R (>= -3) of the first step is loaded into slot R mod NR.
+      // Row R (>= -D) of the first step (moment storage: record row R) is
+      // loaded into slot R mod NR.
       auto fetch_row = [&](int row, auto slot_c) {
         constexpr int k = decltype(slot_c)::value;
         if constexpr (kInPlace)
           s.fetch(row, fa[k], nullptr);
+        else if constexpr (kM)
+          s.fetch_record(row, raw[k]);
         else
           s.fetch(row, raw[k].v, raw[k].q);
       };
       unrolled(std::make_integer_sequence<int, PF>{}, [&](auto k) {
-        fetch_row(-3 + decltype(k)::value,
-                  std::integral_constant<int, (decltype(k)::value + 3 * NR - 3) % NR>{});
+        fetch_row(-D + decltype(k)::value,
+                  std::integral_constant<int, (decltype(k)::value + D * NR - D) % NR>{});
       });
       // March position j with phase u = j mod U: issue the loads of row
-      // j + 3 + PF (the band's last row again past its end); decode row j + 3
-      // and publish psi(t); collide row j + 2 into the ring; pull f(t + 1) of
-      // row j + 1 and publish psi(t + 1); collide row j and store it.
+      // j + D + PF (the band's last row again past its end); decode row j + 3
+      // (moment storage: decode record row j + 4 into the record ring, then
+      // pull row j + 3 from it) and publish psi(t); collide row j + 2 into the
+      // ring; pull f(t + 1) of row j + 1 and publish psi(t + 1); collide row j
+      // and store it.
       auto pos = [&](auto lead_c, auto u_c, int j) {
         constexpr bool kLead = decltype(lead_c)::value;  // j < 0: no output row yet
         constexpr int u = decltype(u_c)::value;
-        constexpr int kd = (u + 3) % NR;  // slot of row j + 3
+        constexpr int kd = (u + D) % NR;  // slot of row j + D
         // ring slot of row j + d (j = u mod U)
         auto ring = [&](int d) { return kFixedRing ? (u + d + 9) % 3 : slot3(j + d); };
         auto ring2 = [&](int d) { return kFixedRing ? (u + d + 10) % 2 : slot2(j + d); };
@@ -1218,13 +1304,52 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
         float(&fa_p)[10] = fa[kInPlace ? (u + 2) % NR : (u + 2) & 1];
         float(&fb_c)[10] = fb[(u + 1) & 1];
         float(&fb_p)[10] = fb[u & 1];
-        fetch_row(min(j + 3 + PF, h + 2), std::integral_constant<int, (u + 3 + PF) % NR>{});
-        if constexpr (kInPlace)
-          fa_c[9] = density(fa_c);
-        else
-          s.decode(raw[kd], fa_c);
-        psa[ring(3)][t] = psi_of(fa_c[9]);
-        if constexpr (DIAG) rr[ring(3)][t] = density64(fa_c);
+        fetch_row(min(j + D + PF, h + D - 1), std::integral_constant<int, (u + D + PF) % NR>{});
+        if constexpr (kM) {
+          // record row j + 4: its nine values, by the side each is pulled to
+          {
+            float a[9];
+            mom_decode(raw[kd].r[0], raw[kd].r[1], raw[kd].r[2], raw[kd].h, a);
+            float(*md)[NT] = amd[ring2(4)];
+            float(*old)[NT] = aold[ring(4)];
+            float(*dn)[NT] = upward ? anew : old;
+            float(*up)[NT] = upward ? old : anew;
+            md[0][t] = a[0];
+            md[1][t] = a[1];
+            md[2][t] = a[3];
+            dn[0][t] = a[2];
+            dn[1][t] = a[5];
+            dn[2][t] = a[6];
+            up[0][t] = a[4];
+            up[1][t] = a[7];
+            up[2][t] = a[8];
+          }
+          __syncthreads();
+          if (!kLead || j >= -6) {  // row j + 3: f_i(x) = A_i(x - e_i)
+            const float(*md)[NT] = amd[ring2(3)];
+            const float(*old)[NT] = aold[ring(2)];
+            const float(*dn)[NT] = upward ? anew : old;
+            const float(*up)[NT] = upward ? old : anew;
+            fa_c[0] = md[0][t];
+            fa_c[1] = md[1][tal];
+            fa_c[2] = dn[0][t];
+            fa_c[3] = md[2][tar];
+            fa_c[4] = up[0][t];
+            fa_c[5] = dn[1][tal];
+            fa_c[6] = dn[2][tar];
+            fa_c[7] = up[1][tar];
+            fa_c[8] = up[2][tal];
+            fa_c[9] = density(fa_c);
+            psa[ring(3)][t] = psi_of(fa_c[9]);
+          }
+        } else {
+          if constexpr (kInPlace)
+            fa_c[9] = density(fa_c);
+          else
+            s.decode(raw[kd], fa_c);
+          psa[ring(3)][t] = psi_of(fa_c[9]);
+          if constexpr (DIAG) rr[ring(3)][t] = density64(fa_c);
+        }
         __syncthreads();
         if constexpr (DIAG) {  // the state read, row j + 2, before its collision
           if ((unsigned)(j + 2) < (unsigned)h && s.out)
@@ -1237,8 +1362,12 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
           const float rho = fa_p[9];
           collide(fa_p, rho, Fx, Fy, s.tau, s.omega);
           float g[9];
+          if constexpr (kM) {
+            F::through_record(fa_p, rho, g);
+          } else {
 #pragma unroll
-          for (int i = 0; i < 9; ++i) g[i] = s.through_storage(fa_p[i], i, rho);
+            for (int i = 0; i < 9; ++i) g[i] = s.through_storage(fa_p[i], i, rho);
+          }
           // Row j + 2 is the row below row j + 1 (populations 2, 5, 6 are
           // pulled from it) when marching upwards, the row above it
           // (populations 4, 7, 8) when marching downwards.
@@ -1285,9 +1414,9 @@ __device__ __forceinline__ void two_step_march(const InstDesc* __restrict__ desc
           s.store(j, fb_p);
         }
       };
-      // six lead-in positions, j = -6 .. -1
-      unrolled(std::make_integer_sequence<int, 6>{}, [&](auto k) {
-        constexpr int j = decltype(k)::value - 6;
+      // 2 D lead-in positions, j = -2 D .. -1
+      unrolled(std::make_integer_sequence<int, 2 * D>{}, [&](auto k) {
+        constexpr int j = decltype(k)::value - 2 * D;
         pos(std::true_type{}, std::integral_constant<int, (j % U + U) % U>{}, j);
       });
       const auto phases = std::make_integer_sequence<int, U>{};
@@ -1759,12 +1888,13 @@ const void* step_fn_t() {
   return reinterpret_cast<const void*>(&k_step<S, NT, CPT, PF>);
 }
 
-// Moment storage runs the strip kernel only: its two-step and paired-column
-// shapes are not valid tiles (tile_valid) and have no kernel.
+// Moment storage has no paired-column kernel, and two-step kernels only for
+// strips of at most NT - 8 columns (four halo columns on each side); the
+// other shapes are not valid tiles for it (tile_valid).
 template <class S, int NT, int PF, int W>
 hipError_t launch_fused_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                           int grid, int sub, hipStream_t st) {
-  if constexpr (S::kMoment) {
+  if constexpr (W > NT - 2 * fused_halo<S>()) {
     return hipErrorInvalidDeviceFunction;
   } else {
     hipLaunchKernelGGL((k_step2<S, NT, PF, W>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
@@ -1775,7 +1905,7 @@ hipError_t launch_fused_t(const InstDesc* descs, const TileItem* items, const in
 
 template <class S, int NT, int PF, int W>
 const void* fused_fn_t() {
-  if constexpr (S::kMoment)
+  if constexpr (W > NT - 2 * fused_halo<S>())
     return nullptr;
   else
     return reinterpret_cast<const void*>(&k_step2<S, NT, PF, W>);

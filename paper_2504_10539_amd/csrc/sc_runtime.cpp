@@ -187,10 +187,18 @@ int default_strip_tile(const lbm_params& p) {
 
 int default_tile(const lbm_params& p) {
   const size_t cells = (size_t)p.nx * (size_t)p.ny;
-  // Moment storage: strips of 256 threads x 1 cell, 2 rows in flight, with
-  // the band heights of the strip defaults.
-  if (p.storage == LBM_F16_MOMENT)
+  // Moment storage: two steps per launch from a million cells (256 threads
+  // writing 240 columns, balanced bands) and on grids up to 512 columns wide
+  // (one periodic strip, balanced bands); strips of 256 threads x 1 cell, 2
+  // rows in flight, with the band heights of the strip defaults otherwise.
+  if (p.storage == LBM_F16_MOMENT) {
+    if (cells >= (1u << 20)) return find_variant(256, 1, 1, 0, 2, 240) * kNumRows + row_choice(0);
+    if (p.nx <= 512) {
+      const int nt = p.nx <= 128 ? 128 : (p.nx <= 256 ? 256 : 512);
+      return find_variant(nt, 1, 1, 0, 2, nt - 16) * kNumRows + row_choice(0);  // 112, 240, 496 columns
+    }
     return find_variant(256, 1, 2, 0) * kNumRows + default_strip_tile(p) % kNumRows;
+  }
   // From a million cells up, two steps per launch: FP32 with 256 threads
   // writing 240 columns (64-byte-aligned strips), 8-row bands; FP16-shifted
   // from 16M cells with 256 threads, 2 rows in flight and balanced bands,
@@ -1121,7 +1129,7 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
     if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
     if (!tile_valid(k, c->p.nx, c->p.storage))
       return fail(LBM_EINVAL, c->p.storage == LBM_F16_MOMENT
-                                  ? "moment storage runs single-step strip tile shapes only"
+                                  ? "moment storage runs strip shapes and two-step shapes of at most threads - 8 columns"
                                   : "paired-column tile shapes need an even nx >= 128");
     if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
     return c->upload_tile(k);

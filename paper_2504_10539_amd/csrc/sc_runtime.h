@@ -78,10 +78,12 @@ inline int find_variant(int threads, int cells, int prefetch, int paired, int st
   return -1;
 }
 // Whether tile shape k can run a grid nx columns wide in this storage form
-// (moment storage runs single-step strip shapes only).
+// (moment storage: strip shapes, and two-step shapes whose strips leave four
+// halo columns on each side).
 inline bool tile_valid(int k, int nx, int storage) {
   const StepVariant& v = step_variant(tile_variant(k));
-  if (storage == LBM_F16_MOMENT && (v.paired || v.steps != 1)) return false;
+  if (storage == LBM_F16_MOMENT && (v.paired || (v.steps == 2 && v.width > v.threads - 8)))
+    return false;
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
 // Whether a batch can use tile shape k.

@@ -118,9 +118,9 @@ constexpr int kMaxBypass = 64;  // a request may be passed at most this often
 // FP32 on 64-byte-aligned 240-column strips, the FP16 forms on 250-column
 // strips (per-cell shift with 2 rows in flight); a request up to 256 columns
 // wide is one periodic strip, and a tail launch takes the odd last step of a
-// tick.  Moment storage takes single-step strips of 256 threads, 2 rows in
-// flight.  Item capacity: every cell of the pool in the narrowest strips and
-// shortest bands, plus a margin per slot.
+// tick.  Moment storage takes the 240-column strips too (its two-step kernel
+// keeps four halo columns on each side).  Item capacity: every cell of the
+// pool in the narrowest strips and shortest bands, plus a margin per slot.
 struct EngineTables {
   int cap_items[kNumStorages], cap_titems[kNumStorages], variants[kNumStorages];
 };
@@ -130,7 +130,7 @@ EngineTables engine_tables(size_t pool_bytes, int max_slots) {
   const int per = (int)std::min<size_t>(
       pool_bytes / (36ull * tile_width(v * kNumRows) * kMinRows) + 64ull * max_slots, 1u << 22);
   const int variants[kNumStorages] = {v, find_variant(256, 1, 1, 0, 2, 250),
-                                      find_variant(256, 1, 2, 0, 2, 250), find_variant(256, 1, 2, 0)};
+                                      find_variant(256, 1, 2, 0, 2, 250), v};
   for (int k = 0; k < kNumStorages; ++k) {
     t.variants[k] = variants[k];
     t.cap_items[k] = per;

@@ -30,3 +30,18 @@ def set_state_from(sim, f: np.ndarray):
 
 def rel_density_error(rho_gpu: np.ndarray, rho_ref: np.ndarray) -> float:
     return float(np.max(np.abs(rho_gpu - rho_ref) / np.abs(rho_ref)))
+
+
+def round_half(q) -> np.float16:
+    """Nearest half-precision value to the exact rational q, ties to even (the
+    per-cell and moment storage forms round each stored deviation once, from
+    the exact difference)."""
+    from fractions import Fraction
+    q = Fraction(q)
+    c = np.float16(float(q))
+    best = None
+    for v in (np.nextafter(c, np.float16(-np.inf)), c, np.nextafter(c, np.float16(np.inf))):
+        d = abs(Fraction(float(v)) - q)
+        if best is None or d < best[0] or (d == best[0] and (v.view(np.uint16) & 1) == 0):
+            best = (d, v)
+    return best[1]

@@ -156,7 +156,7 @@ def test_default_tile(lbm):
     a million cells; below that a grid up to 512 columns wide is one periodic
     two-step strip with balanced bands."""
     tiles = lbm.tiles()
-    for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL):
+    for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL, lbm.LBM_F16_MOMENT):
         for nx, ny in ((1, 1), (64, 64), (97, 300), (128, 128), (256, 256), (300, 77), (512, 512),
                        (513, 100), (1000, 1000), (1024, 1024), (2047, 2048), (4096, 4096)):
             t = tiles[lbm.default_tile(nx, ny, st)]

@@ -1,7 +1,8 @@
 """FP16 storage shifted per cell (LBM_F16_CELL) against the FP64 oracle.
 
 Storage form: the nine values a cell x stores, A_i(x), are kept as
-h_i = half_RNE(fma(-w_i, rhohat, A_i)) with rhohat = half(sum_i A_i) of that
+h_i = half_RNE(A_i - w_i rhohat), rounded once from the exact value, with
+rhohat = half(sum_i A_i) of that
 cell stored in a tenth FP16 plane, and read back as fma(rhohat, w_i, h_i) in
 FP32.  Only the non-equilibrium and velocity parts of the populations round
 to half precision, so the density bar of the FP16 form (1e-3) is within
@@ -14,7 +15,7 @@ import pytest
 
 import oracle
 from paper_2504_10539_amd import inputs
-from tests.gpu_helpers import f32_state, lbm, need_gpu, set_state_from, to_np
+from tests.gpu_helpers import f32_state, lbm, need_gpu, round_half, set_state_from, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +56,7 @@ def _expected_roundtrip(f):
         for y in range(A.shape[1]):
             for x in range(A.shape[2]):
                 q = np.float32(rh[y, x])
-                h = np.float16(_fma32(-W[i], q, A[i, y, x]))
+                h = round_half(-Fraction(float(W[i])) * Fraction(float(q)) + Fraction(float(A[i, y, x])))
                 dec[i, y, x] = _fma32(q, W[i], np.float32(h))
     return np.stack([np.roll(dec[i], (EY[i], EX[i]), axis=(0, 1)) for i in range(9)])
 

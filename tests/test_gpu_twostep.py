@@ -23,8 +23,11 @@ def _gpu():
     need_gpu()
 
 
-def _two_step(rows=None):
-    return [t for t in lbm().tiles() if t["steps"] == 2 and (rows is None or t["rows"] in rows)]
+def _two_step(rows=None, storage=0):
+    """Two-step shapes (moment storage: those whose strips keep four halo
+    columns on each side)."""
+    return [t for t in lbm().tiles() if t["steps"] == 2 and (rows is None or t["rows"] in rows)
+            and (storage != 3 or t["width"] <= t["threads"] - 8)]
 
 
 def _strip_tile():
@@ -37,7 +40,7 @@ def _rho0(storage):
     return 1.0 if storage == lbm().LBM_F16_SHIFTED else 0.0
 
 
-@pytest.mark.parametrize("storage", [0, 1, 2])
+@pytest.mark.parametrize("storage", [0, 1, 2, 3])
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 5), (5, 3), (40, 9), (127, 6), (128, 4),
                                    (250, 2), (251, 13), (254, 3), (255, 6), (256, 7), (300, 77),
                                    (512, 3), (513, 5)])
@@ -53,7 +56,7 @@ def test_two_step_shapes_match_single_step(storage, nx, ny):
     set_state_from(ref, f0)
     ref.step(7)
     want = to_np(ref.get_state())
-    for t in _two_step(rows=(2, 8, 128)):
+    for t in _two_step(rows=(2, 8, 128), storage=storage):
         s = L.Simulation(nx, ny, -5.5, 0.8, storage, _rho0(storage))
         s.set_tile(t["id"])
         set_state_from(s, f0)
@@ -90,7 +93,7 @@ def test_droplet_run_with_two_step_tile_meets_oracle_bar():
     assert float(np.max(np.abs(rho - ref) / ref)) < 1e-5
 
 
-@pytest.mark.parametrize("storage", [0, 2])
+@pytest.mark.parametrize("storage", [0, 2, 3])
 def test_series_with_two_step_tile_is_unchanged(storage):
     """step_series runs its recording steps with the series strip tile and the
     steps between them with the run's tile: records and final state equal
@@ -99,7 +102,7 @@ def test_series_with_two_step_tile_is_unchanged(storage):
     nx, ny = 200, 90
     drops = [(80.0, 45.0, 20.0), (170.0, 20.0, 9.0)]
     runs = []
-    for tile in (_strip_tile(), _two_step(rows=(8,))[1]["id"]):
+    for tile in (_strip_tile(), _two_step(rows=(8,), storage=storage)[1]["id"]):
         s = L.Simulation(nx, ny, -5.5, 1.0, storage, _rho0(storage)).init_droplets(drops, seed=2)
         s.set_tile(tile)
         recs = s.step_series(25, 4)
@@ -141,14 +144,15 @@ def test_two_step_batch_matches_single_step_runs(K):
     single-step run of its own."""
     L = lbm()
     specs = [(130, 70, L.LBM_F32, 0.0), (64, 48, L.LBM_F16_SHIFTED, 1.0),
-             (90, 90, L.LBM_F16_CELL, 0.0), (300, 40, L.LBM_F32, 0.0)]
+             (90, 90, L.LBM_F16_CELL, 0.0), (300, 40, L.LBM_F32, 0.0),
+             (150, 60, L.LBM_F16_MOMENT, 0.0)]
     def make(i, nx, ny, st, r0):
         return L.Simulation(nx, ny, -5.5, 0.9, st, r0).init_droplets([(nx / 2, ny / 2, ny / 4)],
                                                                       seed=10 + i)
     batch = [make(i, *sp) for i, sp in enumerate(specs)]
     solo = [make(i, *sp) for i, sp in enumerate(specs)]
     two = next(t["id"] for t in L.tiles() if t["steps"] == 2 and t["threads"] == 128
-               and t["rows"] == 4)
+               and t["rows"] == 4 and t["width"] == 112)
     for s in batch:
         s.set_tile(two)
     for s in solo:

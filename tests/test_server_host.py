@@ -43,7 +43,7 @@ def test_poll_states_and_results(lbm):
 
 
 def test_rejects_invalid_and_oversized(lbm):
-    s = lbm.Server(4 << 20, fake=True, fake_mlups=1000.0)
+    s = lbm.Server(8 << 20, fake=True, fake_mlups=1000.0)
     with pytest.raises(lbm.LbmError) as e:
         s.submit(64, 64, -5.0, 0.5, 10, [(32, 32, 8)])
     assert e.value.code == lbm.LBM_EINVAL
