@@ -105,6 +105,8 @@ def run_main(args, torch, lbm, inputs):
                           (lbm.LBM_F16_CELL, "f16_cell"), (lbm.LBM_F16_MOMENT, "f16_moment")):
         if storage != lbm.LBM_F32 and args.no_fp16:
             continue
+        if args.storages and name not in args.storages.split(","):
+            continue
         rho0 = 1.0 if storage == lbm.LBM_F16_SHIFTED else 0.0
         sim = lbm.Simulation(N, N, args.G, args.tau, storage, rho0)
         sim.init_droplets(drops, seed=3)
@@ -566,6 +568,9 @@ def main():
     ap.add_argument("--tile", type=int, default=-1, help="fixed tile shape (default: autotune)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-fp16", action="store_true")
+    ap.add_argument("--storages", default="",
+                    help="comma-separated storage legs of the main workload to run "
+                         "(f32, f16_shifted, f16_cell, f16_moment; default: all)")
     ap.add_argument("--no-extras", action="store_true", help="skip sweep, serving and CPU baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -615,6 +620,9 @@ def main():
     log(f"device {torch.cuda.get_device_name(0)}; workload {args.n}^2, {args.drops} droplets, "
         f"G {args.G}, tau {args.tau}, {args.lbm_steps} LBM steps per job")
     main_res = run_main(args, torch, lbm, inputs)
+    if "f32" not in main_res:  # a subset of the storage legs (--storages): their figures only
+        print(json.dumps(main_res), flush=True)
+        return
     f32 = main_res["f32"]
     khash = kernel_source_hash()
     copy_gbs = run_copy_reference(torch, lbm)

@@ -62,12 +62,13 @@ def test_committed_counters_name_real_shapes(lbm):
         d = json.load(fh)
     # balanced shapes (rows 0) take a height per grid and device
     shapes = {(bench.kernel_name(lbm, t["id"], s), t["width"], t["rows"])
-              for t in lbm.tiles() for s in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL)}
+              for t in lbm.tiles()
+              for s in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL, lbm.LBM_F16_MOMENT)}
     assert d["entries"]
     for e in d["entries"]:
         assert ((e["kernel"], e["width"], e["rows"]) in shapes
                 or ((e["kernel"], e["width"], 0) in shapes and 2 <= e["rows"] <= 256)), e
-        bpu = {"f32": 72, "f16_shifted": 36, "f16_cell": 40}[e["storage"]]
+        bpu = {"f32": 72, "f16_shifted": 36, "f16_cell": 40, "f16_moment": 48}[e["storage"]]
         assert e["bytes_per_launch"] > 0.9 * bpu * e["n"] ** 2
 
 
