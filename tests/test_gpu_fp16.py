@@ -80,8 +80,8 @@ def test_config1_fp16_shifted_1000_steps(rho0):
 
 @pytest.mark.xfail(strict=True, reason="one global shift cannot fit both phases: in the gas "
                    "(rho ~ 0.15) the stored f_i - w_i rho0 is of order w_i and its half-precision "
-                   "rounding is ~1e-3 of the local density every step; measured 7.9e-3 (rho0 = 1) "
-                   "and 1.4e-2 (rho0 = 0.5) of rho_max, 2.0e-2 and 3.5e-2 per cell")
+                   "rounding is ~1e-3 of the local density every step; measured 1.35e-2 (rho0 = 1) "
+                   "and 1.6e-2 (rho0 = 0.5) of rho_max, 3.3e-2 and 3.9e-2 per cell")
 @pytest.mark.parametrize("rho0", [0.5, 1.0])
 def test_config1_fp16_shifted_density_bar(rho0):
     """The stated FP16 bar: density within 1e-3 in both readings after 1000 steps."""

@@ -96,9 +96,9 @@ def test_config1_fp16_cell_1000_steps():
     assert m["W"] == mref["W"]
 
 
-@pytest.mark.xfail(strict=True, reason="the per-cell reading of the FP16 bar is missed by a "
-                   "little: 1.1e-3 per cell (4.1e-4 of rho_max); the half-precision rounding of "
-                   "the moving populations leaves mass and momentum errors that move the droplet")
+@pytest.mark.xfail(strict=True, reason="the per-cell reading of the FP16 bar is missed: "
+                   "1.9e-3 per cell (7.7e-4 of rho_max); the half-precision rounding of the "
+                   "moving populations leaves mass and momentum errors that move the droplet")
 def test_config1_fp16_cell_per_cell_density_bar():
     L = lbm()
     N = 64
