@@ -55,9 +55,10 @@ typedef int32_t lbm_status;
 
 /* Population storage. */
 #define LBM_F32 0          /* FP32 populations, 36 bytes per cell per buffer */
-#define LBM_F16_SHIFTED 1  /* FP16 h_i = f_i - w_i rho0 (round to nearest even),
-                              read back as float(h_i) + w_i rho0; 18 bytes per
-                              cell per buffer; arithmetic stays FP32 */
+#define LBM_F16_SHIFTED 1  /* FP16 h_i = f_i - w_i rho0 (the FP32 difference,
+                              then rounded to nearest even), read back as
+                              float(h_i) + w_i rho0; 18 bytes per cell per
+                              buffer; arithmetic stays FP32 */
 #define LBM_F16_CELL 2     /* FP16 shifted per cell: the nine values a cell x
                               stores hold A_i(x) - w_i rhohat(x) (rounded
                               once to nearest even from the exact value), with

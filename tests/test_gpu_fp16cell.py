@@ -44,8 +44,17 @@ def _fma32(a, b, c) -> np.float32:
     return _round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
 
 
-def _expected_roundtrip(f):
-    """get_state(set_state(f)) in the per-cell-shift form, computed exactly on the host."""
+def _twice(q) -> np.float16:
+    """q rounded to FP32 and then to half (the double rounding the storage
+    form does not do)."""
+    return np.float16(_round_f32(Fraction(q)))
+
+
+def _expected_roundtrip(f, to_half=None):
+    """get_state(set_state(f)) in the per-cell-shift form, computed exactly on
+    the host (to_half: the rounding of A_i - w_i rhohat to half, once from the
+    exact value unless another is given for comparison)."""
+    to_half = to_half or round_half
     A = np.stack([np.roll(f[i], (-EY[i], -EX[i]), axis=(0, 1)) for i in range(9)])  # A_i(x) = f_i(x + e_i)
     r = A[0].copy()
     for i in range(1, 9):
@@ -56,7 +65,7 @@ def _expected_roundtrip(f):
         for y in range(A.shape[1]):
             for x in range(A.shape[2]):
                 q = np.float32(rh[y, x])
-                h = round_half(-Fraction(float(W[i])) * Fraction(float(q)) + Fraction(float(A[i, y, x])))
+                h = to_half(-Fraction(float(W[i])) * Fraction(float(q)) + Fraction(float(A[i, y, x])))
                 dec[i, y, x] = _fma32(q, W[i], np.float32(h))
     return np.stack([np.roll(dec[i], (EY[i], EX[i]), axis=(0, 1)) for i in range(9)])
 
@@ -68,6 +77,58 @@ def test_storage_roundtrip_is_cell_shifted_half():
     set_state_from(sim, f)
     got = sim.get_state().cpu().numpy()
     assert np.array_equal(got, _expected_roundtrip(f))
+
+
+def _tie_state(nx, ny, seed):
+    """A state in which one stored difference per cell, A_i - w_i rhohat,
+    lies within half an FP32 ulp of a midpoint between two halves, on the
+    side away from the even one (one rounding and two roundings disagree)."""
+    rng = np.random.default_rng(seed)
+    A = np.empty((9, ny, nx), np.float32)
+    crafted = 0
+    for y in range(ny):
+        for x in range(nx):
+            i = (x + 2 * y) % 9
+            w = Fraction(float(W[i]))
+            for _ in range(400):
+                a = rng.uniform(0.05, 0.3, 9).astype(np.float32)
+                for _ in range(3):  # rhohat = half(rho) moves only if A_i crosses a half
+                    r = np.float32(a[0])
+                    for v in a[1:]:
+                        r = np.float32(r + v)
+                    q = Fraction(float(np.float16(r)))
+                    lo = np.float16(-float(w * q) / 2)
+                    hi = np.nextafter(lo, np.float16(1))
+                    m = (Fraction(float(lo)) + Fraction(float(hi))) / 2
+                    a[i] = np.float32(float(m + w * q))
+                r = np.float32(a[0])
+                for v in a[1:]:
+                    r = np.float32(r + v)
+                d = Fraction(float(a[i])) - w * Fraction(float(np.float16(r)))
+                if d != m and _round_f32(d) == np.float32(float(m)) and round_half(d) != _twice(d):
+                    crafted += 1
+                    break
+            A[:, y, x] = a
+    f = np.stack([np.roll(A[i], (EY[i], EX[i]), axis=(0, 1)) for i in range(9)])
+    return f, crafted
+
+
+def test_cell_shifted_values_are_rounded_once():
+    """Stored values are the nearest halves to the exact differences: on a
+    state built so that one rounding and two roundings (via FP32) disagree in
+    every cell, the round trip equals the single rounding bit for bit and not
+    the double one."""
+    L = lbm()
+    nx, ny = 16, 8
+    f, crafted = _tie_state(nx, ny, seed=22)
+    assert crafted >= nx * ny * 3 // 4
+    sim = L.Simulation(nx, ny, -5.0, 1.0, L.LBM_F16_CELL)
+    set_state_from(sim, f)
+    got = sim.get_state().cpu().numpy()
+    once = _expected_roundtrip(f)
+    twice = _expected_roundtrip(f, _twice)
+    assert np.array_equal(got.view(np.uint32), once.view(np.uint32))
+    assert np.sum(once.view(np.uint32) != twice.view(np.uint32)) >= crafted
 
 
 def test_config1_fp16_cell_1000_steps():

@@ -48,11 +48,19 @@ def _fma32(a, b, c) -> np.float32:
     return _round_f32(Fraction(float(a)) * Fraction(float(b)) + Fraction(float(c)))
 
 
-def _expected_roundtrip(f):
+def _twice(q) -> np.float16:
+    """q rounded to FP32 and then to half (the double rounding the storage
+    form does not do)."""
+    return np.float16(_round_f32(Fraction(q)))
+
+
+def _expected_roundtrip(f, to_half=None):
     """get_state(set_state(f)) in the moment form, computed exactly on the host:
     FP32 sums and differences in numpy (IEEE, round to nearest even), the fused
     multiply-adds in exact rational arithmetic rounded once, and each stored
-    deviation rounded once to half from the exact A_i - w_i rho."""
+    deviation rounded once to half from the exact A_i - w_i rho (to_half:
+    another rounding of that difference, for comparison)."""
+    to_half = to_half or round_half
     A = np.stack([np.roll(f[i], (-EY[i], -EX[i]), axis=(0, 1)) for i in range(9)])  # A_i(x) = f_i(x + e_i)
     ny, nx = A.shape[1:]
     rho = A[0].copy()
@@ -66,7 +74,7 @@ def _expected_roundtrip(f):
         for x in range(nx):
             r = rho[y, x]
             for i in range(3, 9):
-                h = round_half(-Fraction(float(W[i])) * Fraction(float(r)) + Fraction(float(A[i, y, x])))
+                h = to_half(-Fraction(float(W[i])) * Fraction(float(r)) + Fraction(float(A[i, y, x])))
                 dec[i, y, x] = _fma32(r, W[i], np.float32(h))
     d, e = (dec[5] - dec[7]).astype(f32), (dec[8] - dec[6]).astype(f32)
     dec[1] = ((jx + dec[3]).astype(f32) - (d + e).astype(f32)).astype(f32)
@@ -84,6 +92,65 @@ def test_storage_roundtrip_is_the_moment_record():
     set_state_from(sim, f)
     got = sim.get_state().cpu().numpy()
     assert np.array_equal(got.view(np.uint32), _expected_roundtrip(f).view(np.uint32))
+
+
+def _density32(a):
+    r = np.float32(a[0])
+    for v in a[1:]:
+        r = np.float32(r + np.float32(v))
+    return r
+
+
+def _tie_state(nx, ny, seed):
+    """A state in which one deviation per cell, A_i - w_i rho (i = 3..8), lies
+    within half an FP32 ulp of a midpoint between two halves, on the side
+    away from the even one: rounded once it goes to the odd half, rounded to
+    FP32 first it lands on the midpoint and then on the even half."""
+    rng = np.random.default_rng(seed)
+    A = np.empty((9, ny, nx), np.float32)
+    crafted = 0
+    for y in range(ny):
+        for x in range(nx):
+            i = 3 + (x + y) % 6
+            w = Fraction(float(W[i]))
+            for _ in range(400):
+                a = rng.uniform(0.05, 0.3, 9).astype(np.float32)
+                # a midpoint of two halves near -w rho / 2, so that A_i and the
+                # difference share a binade
+                lo = np.float16(-float(w) * float(_density32(a)) / 2)
+                hi = np.nextafter(lo, np.float16(1))
+                m = (Fraction(float(lo)) + Fraction(float(hi))) / 2
+                # A_i = m + w rho with rho = (the others) + A_i, then the FP32
+                # sum order settled
+                others = Fraction(float(_density32(a))) - Fraction(float(a[i]))
+                a[i] = np.float32(float((m + w * others) / (1 - w)))
+                for _ in range(4):
+                    a[i] = np.float32(float(m + w * Fraction(float(_density32(a)))))
+                d = Fraction(float(a[i])) - w * Fraction(float(_density32(a)))
+                if d != m and _round_f32(d) == np.float32(float(m)) and round_half(d) != _twice(d):
+                    crafted += 1
+                    break
+            A[:, y, x] = a
+    f = np.stack([np.roll(A[i], (EY[i], EX[i]), axis=(0, 1)) for i in range(9)])  # f_i(x) = A_i(x - e_i)
+    return f, crafted
+
+
+def test_moment_deviations_are_rounded_once():
+    """Stored deviations are the nearest halves to the exact differences: on a
+    state built so that one rounding and two roundings (via FP32) disagree in
+    every cell, the round trip equals the single rounding bit for bit and not
+    the double one."""
+    L = lbm()
+    nx, ny = 16, 8
+    f, crafted = _tie_state(nx, ny, seed=21)
+    assert crafted >= nx * ny * 3 // 4
+    sim = L.Simulation(nx, ny, -5.0, 1.0, L.LBM_F16_MOMENT)
+    set_state_from(sim, f)
+    got = sim.get_state().cpu().numpy()
+    once = _expected_roundtrip(f)
+    twice = _expected_roundtrip(f, _twice)
+    assert np.array_equal(got.view(np.uint32), once.view(np.uint32))
+    assert np.sum(once.view(np.uint32) != twice.view(np.uint32)) >= crafted
 
 
 def test_config1_fp16_moment_meets_the_density_bar():
