@@ -78,6 +78,8 @@ def kernel_name(lbm, tile: int, storage: int) -> str:
     t = lbm.tiles()[tile]
     st = {lbm.LBM_F32: "StoreF32", lbm.LBM_F16_SHIFTED: "StoreF16S", lbm.LBM_F16_CELL: "StoreF16C",
           lbm.LBM_F16_MOMENT: "StoreF16M"}[storage]
+    if t["steps"] == 3:  # FP32 only
+        return f"k_step3<{t['threads']}, {t['prefetch']}, {t['width']}>"
     if t["steps"] == 2:
         return f"k_step2<{st}, {t['threads']}, {t['prefetch']}, {t['width']}>"
     if t["paired"]:

@@ -14,11 +14,12 @@ namespace sclbm {
 // NT * CPT columns per workgroup; paired-column variants (paired = 1, CPT = 2)
 // cover kPairColumns per wavefront and need an even nx >= 128.  Two-step
 // variants (steps = 2, CPT = 1) advance `width` <= NT - kFusedHalo columns by
-// two time steps per launch (0 for the other kinds).
+// two time steps per launch, three-step variants (steps = 3, FP32 only)
+// `width` <= NT - 10 columns by three (0 for the other kinds).
 struct StepVariant {
   int threads, cells, prefetch, paired, steps, width;
 };
-constexpr int kNumVariants = 29;
+constexpr int kNumVariants = 33;
 constexpr int kFusedHalo = 6;
 constexpr int kPairColumns = 124;
 constexpr int kPairMinNx = 128;

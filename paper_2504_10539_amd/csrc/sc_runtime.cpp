@@ -199,14 +199,20 @@ int default_tile(const lbm_params& p) {
     }
     return find_variant(256, 1, 2, 0) * kNumRows + default_strip_tile(p) % kNumRows;
   }
-  // From a million cells up, two steps per launch: FP32 with 256 threads
-  // writing 240 columns (64-byte-aligned strips), 8-row bands; FP16-shifted
+  // From a million cells up, FP32 takes three steps per launch: 256 threads
+  // writing 240 columns (64-byte-aligned strips) in 32-row bands from 16M
+  // cells, 128 threads writing 112 columns below that (32-row bands from 4M
+  // cells, 8-row below).  The FP16 forms take two steps per launch: shifted
   // from 16M cells with 256 threads, 2 rows in flight and balanced bands,
   // below that with 128 threads (8-row bands below 4M cells, else balanced);
   // FP16 shifted per cell with 256 threads and 2 rows in flight (balanced
   // bands from 16M cells, 16-row from 4M, 8-row below).
   if (cells >= (1u << 20)) {
-    if (p.storage == LBM_F32) return find_variant(256, 1, 1, 0, 2, 240) * kNumRows + row_choice(8);
+    if (p.storage == LBM_F32) {
+      if (cells >= (16u << 20)) return find_variant(256, 1, 1, 0, 3, 240) * kNumRows + row_choice(32);
+      return find_variant(128, 1, 1, 0, 3, 112) * kNumRows +
+             row_choice(cells >= (4u << 20) ? 32 : 8);
+    }
     if (p.storage == LBM_F16_SHIFTED && cells >= (16u << 20))
       return find_variant(256, 1, 2, 0, 2) * kNumRows + row_choice(0);
     if (p.storage == LBM_F16_SHIFTED)
@@ -776,6 +782,9 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
       widest = c;
     }
   if (best < 0) return best;
+  // a three-step member tile: the two-step variant of the same strips
+  const StepVariant& bv = step_variant(best);
+  if (bv.steps == 3) best = find_variant(bv.threads, 1, bv.prefetch, 0, 2, bv.width);
   for (lbm_ctx* c : m)
     if (c->p.storage == storage && !tile_batchable(best * kNumRows, c->p.nx, storage))
       return tile_variant(default_strip_tile(widest->p));

@@ -53,7 +53,7 @@ inline int tile_variant(int k) { return k / kNumRows; }
 inline int tile_rows(int k) { return kRowChoices[k % kNumRows]; }  // 0: balanced
 inline int tile_width(int k) {
   const StepVariant& v = step_variant(tile_variant(k));
-  if (v.steps == 2) return v.width;
+  if (v.steps >= 2) return v.width;
   return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
 }
 // Columns one work item of tile shape k covers on a grid nx columns wide: a
@@ -61,7 +61,7 @@ inline int tile_width(int k) {
 // strip.
 inline int strip_width(int k, int nx) {
   const StepVariant& v = step_variant(tile_variant(k));
-  return v.steps == 2 && nx <= v.threads ? nx : tile_width(k);
+  return v.steps >= 2 && nx <= v.threads ? nx : tile_width(k);
 }
 // Time steps one launch of tile shape k takes.
 inline int tile_steps(int k) { return step_variant(tile_variant(k)).steps; }
@@ -79,15 +79,19 @@ inline int find_variant(int threads, int cells, int prefetch, int paired, int st
 }
 // Whether tile shape k can run a grid nx columns wide in this storage form
 // (moment storage: strip shapes, and two-step shapes whose strips leave four
-// halo columns on each side).
+// halo columns on each side; three-step shapes: FP32 only).
 inline bool tile_valid(int k, int nx, int storage) {
   const StepVariant& v = step_variant(tile_variant(k));
+  if (v.steps == 3 && storage != LBM_F32) return false;
   if (storage == LBM_F16_MOMENT && (v.paired || (v.steps == 2 && v.width > v.threads - 8)))
     return false;
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
-// Whether a batch can use tile shape k.
-inline bool tile_batchable(int k, int nx, int storage) { return tile_valid(k, nx, storage); }
+// Whether a batch can use tile shape k (batches take one or two steps per
+// launch).
+inline bool tile_batchable(int k, int nx, int storage) {
+  return tile_steps(k) <= 2 && tile_valid(k, nx, storage);
+}
 
 // Band height tile shape k uses on an nx x ny grid of this storage type
 // (balanced shapes: from the step kernel's occupancy on the current device).

@@ -105,13 +105,16 @@ def test_tile_table(lbm):
     tiles = lbm.tiles()
     assert len(tiles) == lbm.LIB.lbm_tile_count()
     assert all(t["width"] >= 64 and (t["rows"] >= 2 or t["rows"] == 0) for t in tiles)
-    assert len({(t["width"], t["rows"], t["threads"], t["prefetch"]) for t in tiles}) == len(tiles)
+    assert len({(t["width"], t["rows"], t["threads"], t["prefetch"], t["steps"]) for t in tiles}) == len(tiles)
     w = ctypes.c_int32()
     assert lbm.LIB.lbm_tile_describe(len(tiles), ctypes.byref(w), None, None, None, None,
                                      None, None) == lbm.LBM_EINVAL
     for t in tiles:
-        assert t["steps"] in (1, 2)
-        if t["steps"] == 2:  # three halo columns on each side of the strip
+        assert t["steps"] in (1, 2, 3)
+        if t["steps"] == 3:  # five halo columns on each side, 64-byte-aligned FP32 strips
+            assert not t["paired"] and t["cells"] == 1
+            assert t["width"] <= t["threads"] - 10 and t["width"] % 16 == 0
+        elif t["steps"] == 2:  # three halo columns on each side of the strip
             assert not t["paired"] and t["cells"] == 1
             assert t["width"] == t["threads"] - 6 or (t["width"] < t["threads"] - 6
                                                       and t["width"] % 16 == 0)
@@ -119,7 +122,7 @@ def test_tile_table(lbm):
             assert t["cells"] == 2 and t["width"] == t["threads"] // 64 * 124
         else:
             assert t["width"] == t["threads"] * t["cells"]
-    assert any(t["steps"] == 2 for t in tiles)
+    assert any(t["steps"] == 2 for t in tiles) and any(t["steps"] == 3 for t in tiles)
 
 
 def test_tile_layout(lbm):
@@ -134,13 +137,13 @@ def test_tile_layout(lbm):
         else:
             assert 2 <= rows <= 256
         assert items == -(-300 // t["width"]) * -(-77 // rows)
-    # a grid no wider than a two-step workgroup is one periodic strip
+    # a grid no wider than a multi-step workgroup is one periodic strip
     for t in tiles:
         if t["rows"] != 8:
             continue
         for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL):
             rows, items = lbm.tile_layout(256, 64, t["id"], st)
-            one = t["steps"] == 2 and t["threads"] >= 256
+            one = t["steps"] >= 2 and t["threads"] >= 256
             assert items == (1 if one else -(-256 // t["width"])) * 8, (t, st)
     bal = next(t for t in tiles if t["rows"] == 0 and t["steps"] == 2 and t["threads"] == 256)
     rows, items = lbm.tile_layout(4096, 4096, bal["id"], lbm.LBM_F16_SHIFTED)
@@ -152,9 +155,10 @@ def test_tile_layout(lbm):
 
 
 def test_default_tile(lbm):
-    """Built-in shapes: a valid shape for every grid; two steps per launch from
-    a million cells; below that a grid up to 512 columns wide is one periodic
-    two-step strip with balanced bands."""
+    """Built-in shapes: a valid shape for every grid; from a million cells three
+    steps per launch with FP32 storage, two with the FP16 forms; below that a
+    grid up to 512 columns wide is one periodic two-step strip with balanced
+    bands."""
     tiles = lbm.tiles()
     for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL, lbm.LBM_F16_MOMENT):
         for nx, ny in ((1, 1), (64, 64), (97, 300), (128, 128), (256, 256), (300, 77), (512, 512),
@@ -163,7 +167,7 @@ def test_default_tile(lbm):
             if t["paired"]:
                 assert nx % 2 == 0 and nx >= 128, (nx, ny, st, t)
             if nx * ny >= 1 << 20:
-                assert t["steps"] == 2, (nx, ny, st, t)
+                assert t["steps"] == (3 if st == lbm.LBM_F32 else 2), (nx, ny, st, t)
             elif nx <= 512:
                 assert t["steps"] == 2 and t["threads"] >= nx and t["rows"] == 0, (nx, ny, st, t)
     k = ctypes.c_int32()
