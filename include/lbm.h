@@ -274,6 +274,20 @@ int32_t lbm_get_tile(const lbm_ctx* ctx);
  * Synchronises.  *best (may be NULL) receives the chosen shape. */
 lbm_status lbm_autotune(lbm_ctx* ctx, int32_t reps, int32_t* best);
 
+/* lbm_autotune timed as the run steps: the state is first copied to
+ * `scratch` (caller-owned device memory of at least lbm_buffer_bytes'
+ * pop_bytes, 256-byte aligned, borrowed for the call), each shape then
+ * advances the run `reps` launches with the buffers alternating (every
+ * launch reads what the previous one wrote), and afterwards the state, the
+ * buffer holding it and the step count are restored.  On grids whose two
+ * buffers fit the GPU's caches, repeated launches over one unchanged buffer
+ * run faster than stepping does, and by a different amount per shape; this
+ * entry point measures what stepping costs.  Same selection and tuning cache
+ * as lbm_autotune.  LBM_EINVAL for a NULL or unaligned scratch, LBM_ENOMEM
+ * when scratch_bytes is too small.  Synchronises. */
+lbm_status lbm_autotune_stepping(lbm_ctx* ctx, int32_t reps, void* scratch, size_t scratch_bytes,
+                                 int32_t* best);
+
 /* ------------------------------------------------------------ batched runs */
 
 /* Workspace needed to advance the n contexts together. */

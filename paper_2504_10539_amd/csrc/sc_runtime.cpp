@@ -229,10 +229,12 @@ int default_tile(const lbm_params& p) {
     const int nt = p.nx <= 128 && !percell ? 128 : (p.nx <= 256 ? 256 : 512);
     return find_variant(nt, 1, percell ? 2 : 1, 0, 2) * kNumRows + row_choice(0);
   }
-  // FP16 storage below a million cells on grids wider than 512 columns:
+  // Below a million cells on grids wider than 512 columns: FP32 three steps
+  // per launch (128 threads writing 112 columns, 8-row bands); FP16 storage
   // paired columns, 4 wavefronts, 2 rows in flight, 2-row bands, where the
   // grid allows it.
-  if (p.storage != LBM_F32) {
+  if (p.storage == LBM_F32) return find_variant(128, 1, 1, 0, 3, 112) * kNumRows + row_choice(8);
+  {
     const int k = find_variant(256, 2, 2, 1) * kNumRows + row_choice(2);
     if (tile_valid(k, p.nx, p.storage)) return k;
   }
@@ -1147,51 +1149,96 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
 
 int32_t lbm_get_tile(const lbm_ctx* c) { return c ? c->tile : -1; }
 
-lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
-  return guarded("lbm_autotune", [&]() -> lbm_status {
-    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
-    if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
-    if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
-    hipEvent_t e0, e1;
-    SCLBM_HIP(hipEventCreate(&e0));
-    SCLBM_HIP(hipEventCreate(&e1));
-    int best = c->tile;
-    double best_ms = 1e300;
-    lbm_status st = LBM_OK;
-    for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
-      if (!tile_valid(k, c->p.nx, c->p.storage)) continue;
-      st = c->upload_tile(k);
+// Times every valid tile shape on c's grid and selects the fastest per time
+// step.  Without scratch, `reps` launches per shape read the current buffer
+// and write the idle one (the state is untouched).  With scratch (>= the
+// state's bytes) the state is copied there first, each shape advances the run
+// as stepping does (every launch reads what the previous one wrote), and the
+// state, its buffer and the step count are restored afterwards.
+static lbm_status autotune_run(lbm_ctx* c, int32_t reps, void* scratch, int32_t* best_out) {
+  if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+  if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
+  if (reps < 1) return fail(LBM_EINVAL, "reps must be >= 1");
+  const size_t state_bytes = pop_bytes_for(c->p);
+  const int parity0 = c->parity;
+  const int64_t steps0 = c->steps;
+  if (scratch)
+    SCLBM_HIP(hipMemcpyAsync(scratch, c->pop[parity0], state_bytes, hipMemcpyDeviceToDevice,
+                             c->stream));
+  hipEvent_t e0, e1;
+  SCLBM_HIP(hipEventCreate(&e0));
+  SCLBM_HIP(hipEventCreate(&e1));
+  int best = c->tile;
+  double best_ms = 1e300;
+  lbm_status st = LBM_OK;
+  for (int k = 0; k < kNumTiles && st == LBM_OK; ++k) {
+    if (!tile_valid(k, c->p.nx, c->p.storage)) continue;
+    st = c->upload_tile(k);
+    if (st != LBM_OK) break;
+    const int v = tile_variant(k);
+    const int per = tile_steps(k);
+    hipError_t e = hipSuccess;
+    if (scratch) {
+      st = c->advance(per);  // the first launch of the shape, untimed
+      if (st == LBM_OK) e = hipEventRecord(e0, c->stream);
+      if (st == LBM_OK && e == hipSuccess) st = c->advance((int64_t)reps * per);
       if (st != LBM_OK) break;
-      const int v = tile_variant(k);
+    } else {
       // Read the current buffer and write the idle one, leaving the state as is.
-      hipError_t e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
-                                 c->parity, c->stream);
+      e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems, c->parity,
+                      c->stream);
       if (e == hipSuccess) e = hipEventRecord(e0, c->stream);
       for (int r = 0; r < reps && e == hipSuccess; ++r)
-        e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems, c->parity,
-                        c->stream);
-      if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-      if (e == hipSuccess) e = hipEventSynchronize(e1);
-      float ms = 0.f;
-      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-      if (e != hipSuccess) {
-        st = hip_fail(e, "autotune launch");
-        break;
-      }
-      const double per = ms / reps / tile_steps(k);  // per time step
-      if (per < best_ms) {
-        best_ms = per;
-        best = k;
-      }
+        e = launch_step(c->p.storage, v, c->d_desc, c->d_items, c->d_nitems, c->nitems,
+                        c->parity, c->stream);
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (st != LBM_OK) return st;
-    st = c->upload_tile(best);
-    if (st != LBM_OK) return st;
-    record_tuned_tile(c->p, c->arch, best, best_ms);
-    if (best_out) *best_out = best;
-    return LBM_OK;
+    if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "autotune launch");
+      break;
+    }
+    const double per_step = ms / reps / per;
+    if (per_step < best_ms) {
+      best_ms = per_step;
+      best = k;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (scratch) {
+    // the state back in the buffer it started in, whatever the loop reached
+    c->parity = parity0;
+    c->steps = steps0;
+    const hipError_t e = hipMemcpyAsync(c->pop[parity0], scratch, state_bytes,
+                                        hipMemcpyDeviceToDevice, c->stream);
+    if (st == LBM_OK && e != hipSuccess) st = hip_fail(e, "autotune restore");
+    const hipError_t e2 = hipStreamSynchronize(c->stream);
+    if (st == LBM_OK && e2 != hipSuccess) st = hip_fail(e2, "hipStreamSynchronize");
+  }
+  if (st != LBM_OK) return st;
+  st = c->upload_tile(best);
+  if (st != LBM_OK) return st;
+  record_tuned_tile(c->p, c->arch, best, best_ms);
+  if (best_out) *best_out = best;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx* c, int32_t reps, int32_t* best_out) {
+  return guarded("lbm_autotune",
+                 [&]() -> lbm_status { return autotune_run(c, reps, nullptr, best_out); });
+}
+
+lbm_status lbm_autotune_stepping(lbm_ctx* c, int32_t reps, void* scratch, size_t scratch_bytes,
+                                 int32_t* best_out) {
+  return guarded("lbm_autotune_stepping", [&]() -> lbm_status {
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!scratch) return fail(LBM_EINVAL, "scratch is NULL");
+    if ((uintptr_t)scratch & 255) return fail(LBM_EINVAL, "scratch must be 256-byte aligned");
+    if (scratch_bytes < pop_bytes_for(c->p)) return fail(LBM_ENOMEM, "scratch smaller than the state");
+    return autotune_run(c, reps, scratch, best_out);
   });
 }
 

@@ -130,6 +130,7 @@ _PROTOS = {
     "lbm_set_tile": (_i32, [_vp, _i32]),
     "lbm_get_tile": (_i32, [_vp]),
     "lbm_autotune": (_i32, [_vp, _i32, _P(_i32)]),
+    "lbm_autotune_stepping": (_i32, [_vp, _i32, _vp, _sz, _P(_i32)]),
     "lbm_batch_work_bytes": (_i32, [_P(_vp), _i32, _P(_sz)]),
     "lbm_batch_create": (_i32, [_P(_vp), _i32, _vp, _sz, _i32, _P(_vp)]),
     "lbm_batch_step_n": (_i32, [_vp, _i64]),
@@ -392,9 +393,22 @@ class Simulation:
     def tile(self) -> int:
         return int(LIB.lbm_get_tile(self.handle))
 
-    def autotune(self, reps: int = 5) -> int:
+    def autotune(self, reps: int = 5, stepping: bool = True) -> int:
+        """Selects the fastest tile shape.  stepping=True times the shapes as
+        the run steps (lbm_autotune_stepping, with a scratch copy of the state
+        allocated here for the call); False times repeated launches over the
+        unchanged state (lbm_autotune)."""
         best = _i32()
-        _check(LIB.lbm_autotune(self.handle, int(reps), ctypes.byref(best)), "lbm_autotune")
+        if not stepping:
+            _check(LIB.lbm_autotune(self.handle, int(reps), ctypes.byref(best)), "lbm_autotune")
+            return best.value
+        pop = _sz()
+        _check(LIB.lbm_buffer_bytes(ctypes.byref(self.params), ctypes.byref(pop), None),
+               "lbm_buffer_bytes")
+        scratch = _bytes_tensor(pop.value, self.device)
+        _check(LIB.lbm_autotune_stepping(self.handle, int(reps), _dev_ptr(scratch), pop.value,
+                                         ctypes.byref(best)), "lbm_autotune_stepping")
+        del scratch
         return best.value
 
     def close(self):

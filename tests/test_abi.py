@@ -158,7 +158,7 @@ def test_default_tile(lbm):
     """Built-in shapes: a valid shape for every grid; from a million cells three
     steps per launch with FP32 storage, two with the FP16 forms; below that a
     grid up to 512 columns wide is one periodic two-step strip with balanced
-    bands."""
+    bands, and a wider FP32 grid takes three steps per launch."""
     tiles = lbm.tiles()
     for st in (lbm.LBM_F32, lbm.LBM_F16_SHIFTED, lbm.LBM_F16_CELL, lbm.LBM_F16_MOMENT):
         for nx, ny in ((1, 1), (64, 64), (97, 300), (128, 128), (256, 256), (300, 77), (512, 512),
@@ -170,6 +170,8 @@ def test_default_tile(lbm):
                 assert t["steps"] == (3 if st == lbm.LBM_F32 else 2), (nx, ny, st, t)
             elif nx <= 512:
                 assert t["steps"] == 2 and t["threads"] >= nx and t["rows"] == 0, (nx, ny, st, t)
+            elif st == lbm.LBM_F32:
+                assert t["steps"] == 3, (nx, ny, st, t)
     k = ctypes.c_int32()
     p = lbm.make_params(0, 64, -5.0, 1.0)
     assert lbm.LIB.lbm_default_tile(ctypes.byref(p), ctypes.byref(k)) == lbm.LBM_EINVAL

@@ -7,6 +7,8 @@ one step from an identical FP32-representable state agrees to FP32 rounding
 max |drho|/rho <= 1e-5; tile shapes, repeats and translations are bitwise.
 Method: Li & Zhang, arXiv 2504.10539, Sec. II-A Eq. (1), Sec. III-A.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -194,3 +196,47 @@ def test_autotune_keeps_state_and_result(tmp_path, monkeypatch):
     b.step(10)
     assert np.array_equal(to_np(a.get_state()), to_np(b.get_state()))
     assert (tmp_path / "tune.jsonl").read_text().count("\n") == 1
+
+
+@pytest.mark.parametrize("storage", [0, 1, 2, 3])
+def test_stepping_autotune_restores_state_buffer_and_count(tmp_path, monkeypatch, storage):
+    """The stepping autotuner advances the run shape by shape and then puts
+    back the state (every storage form's full record, in the buffer it
+    started in) and the step count; both autotuners are checked from an odd
+    buffer parity."""
+    monkeypatch.setenv("SCLBM_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    L = lbm()
+    nx, ny = 200, 72
+    mk = lambda: L.Simulation(nx, ny, -5.0, 1.0, storage, 1.0 if storage == 1 else 0.0).init_droplets(
+        [(90.0, 36.0, 14.0)], seed=4)
+    a, ref = mk(), mk()
+    one = next(t["id"] for t in L.tiles() if t["steps"] == 1 and not t["paired"])
+    a.set_tile(one)
+    a.step(1)  # one launch: the state is in popB
+    ref.step(1)
+    raw_b = a.popB.clone()
+    for stepping in (True, False):
+        best = a.autotune(reps=2, stepping=stepping)
+        assert 0 <= best < len(L.tiles()) and a.tile == best
+        assert a.steps == 1
+        assert torch.equal(a.popB, raw_b)
+    a.step(11)
+    ref.step(11)
+    assert a.steps == ref.steps == 12
+    assert torch.equal(a.get_state(), ref.get_state())
+
+
+def test_stepping_autotune_refuses_bad_scratch():
+    L = lbm()
+    s = L.Simulation(64, 64, -5.0, 1.0).init_droplets([(32.0, 32.0, 10.0)], seed=1)
+    pop = L._sz()
+    assert L.LIB.lbm_buffer_bytes(ctypes.byref(s.params), ctypes.byref(pop), None) == 0
+    buf = torch.empty(pop.value + 512, dtype=torch.uint8, device="cuda")
+    best = ctypes.c_int32()
+    assert L.LIB.lbm_autotune_stepping(s.handle, 1, buf.data_ptr(), pop.value - 16,
+                                       ctypes.byref(best)) == L.LBM_ENOMEM
+    assert L.LIB.lbm_autotune_stepping(s.handle, 1, buf.data_ptr() + 16, pop.value,
+                                       ctypes.byref(best)) == L.LBM_EINVAL
+    assert L.LIB.lbm_autotune_stepping(s.handle, 1, None, pop.value, ctypes.byref(best)) == L.LBM_EINVAL
+    assert L.LIB.lbm_autotune_stepping(s.handle, 0, buf.data_ptr(), pop.value,
+                                       ctypes.byref(best)) == L.LBM_EINVAL
