@@ -13,10 +13,14 @@ non-finite within about 100 steps, in the FP64 oracle as on the GPU).
 Populations are FP32; the arithmetic is FP32.
 
 `value` is lattice updates per second (MLUPS) of the whole job with the inputs
-resident; `roofline` prices the step kernel (the dominant kernel) at 72
-algorithmic bytes per lattice update against the 8 TB/s HBM peak, with the
-kernel's average launch time measured by HIP events on its stream over the
-timed region.  Extra objects report the FP16-shifted storage, a 1024^2
+resident; `roofline` prices the step kernel (the dominant kernel), with its
+average launch time measured by HIP events on its stream over the timed
+region.  A kernel that moves the populations once per one or two updates is
+priced at 72 algorithmic bytes per launch and cell against the 8 TB/s HBM
+peak; one that takes three updates per launch is bound by its vector ALU
+work and is priced at 106 algorithmic FP32 operations per lattice update
+against the vector issue peak (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3
+T lane operations per second without packed FP32), its HBM figures beside.  Extra objects report the FP16-shifted storage, a 1024^2
 single-droplet run, the paper's own droplet protocol (Tables I-II layout), the
 batched parameter sweep, the serving loop and the FP64 oracle's CPU rate.
 """
@@ -34,6 +38,11 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector operations of one lattice update (density 8, psi 7, force 13,
+# momentum 8, 1/rho 3, velocity 4, u^2 term 3, weights 4, the four
+# equilibrium pairs 30, f_eq_0 8, relaxation 18); an FMA counts as one
+ALU_OPS_PER_UPDATE = 106
+ALU_PEAK_GOPS = 256 * 4 * 16 * 2.4  # lane operations per ns (one per lane per clock)
 BYTES_F32 = 72   # 9 populations read + 9 written, 4 bytes each
 BYTES_F16 = 36
 BYTES_F16_CELL = 40  # 18 B read + 18 B written, plus the 2-byte reference density each way
@@ -78,8 +87,8 @@ def kernel_name(lbm, tile: int, storage: int) -> str:
     t = lbm.tiles()[tile]
     st = {lbm.LBM_F32: "StoreF32", lbm.LBM_F16_SHIFTED: "StoreF16S", lbm.LBM_F16_CELL: "StoreF16C",
           lbm.LBM_F16_MOMENT: "StoreF16M"}[storage]
-    if t["steps"] == 3:  # FP32 only
-        return f"k_step3<{t['threads']}, {t['prefetch']}, {t['width']}>"
+    if t["steps"] >= 3:  # FP32 only
+        return f"k_step{t['steps']}<{t['threads']}, {t['prefetch']}, {t['width']}>"
     if t["steps"] == 2:
         return f"k_step2<{st}, {t['threads']}, {t['prefetch']}, {t['width']}>"
     if t["paired"]:
@@ -96,6 +105,21 @@ def launch_figures(lbm, tile: int, step_ms: float, bytes_per_update: int, cells:
     launch_ms = step_ms * spl
     gbs = bytes_per_update * cells / (launch_ms * 1e-3) / 1e9
     return {"steps_per_launch": spl, "launch_ms": launch_ms, "achieved_gbs": gbs}
+
+
+def roofline_bound(r: dict) -> dict:
+    """Bound, achieved rate, peak and fraction of the step kernel of leg r.
+    Three updates per launch: the vector ALU (algorithmic operations per
+    launch / launch time against the issue peak), with the per-launch HBM
+    figures beside; otherwise HBM (72 algorithmic bytes per cell and launch)."""
+    hbm = {"achieved": round(r["achieved_gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(r["achieved_gbs"] / HBM_PEAK_GBS, 4)}
+    if r["steps_per_launch"] < 3:
+        return dict(bound="hbm", **hbm)
+    gops = ALU_OPS_PER_UPDATE * r["steps_per_launch"] * r["cells"] / (r["launch_ms"] * 1e6)
+    return {"bound": "alu", "achieved": round(gops, 1), "peak": round(ALU_PEAK_GOPS, 1),
+            "unit": "Gop/s", "frac": round(gops / ALU_PEAK_GOPS, 4),
+            "ops_per_update": ALU_OPS_PER_UPDATE, "hbm": hbm}
 
 
 def run_main(args, torch, lbm, inputs):
@@ -158,6 +182,7 @@ def run_main(args, torch, lbm, inputs):
             "launch_ms": lf["launch_ms"],
             "achieved_gbs": lf["achieved_gbs"],
             "bytes_per_update": bpu,
+            "cells": N * N,
             # throughput over the HBM bound of a one-step-per-launch kernel
             "over_one_step_roofline": N * N / (per_step_ms * 1e-3) / (HBM_PEAK_GBS * 1e9 / bpu),
             "tile": sim.tile,
@@ -647,19 +672,17 @@ def main():
                    "droplets": args.drops, "radius": [8, 48], "G": args.G, "tau": args.tau,
                    "lbm_steps_per_step": args.lbm_steps, "storage": "f32",
                    "parallelism": "single_gpu"},
-        "roofline": {"bound": "hbm", "achieved": round(f32["achieved_gbs"], 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(f32["achieved_gbs"] / HBM_PEAK_GBS, 4),
+        "roofline": dict(roofline_bound(f32), **{
                      "traffic": traffic, "kernel": f32["kernel"],
                      "bytes_per_launch_per_cell": BYTES_F32,
                      "steps_per_launch": f32["steps_per_launch"],
                      "launch_ms": round(f32["launch_ms"], 5),
                      # per update instead of per launch: MLUPS x 72 B / 8 TB/s (above 1
-                     # because a two-step launch moves each population once per two updates)
+                     # because a multi-step launch moves each population once per K updates)
                      "over_one_step_roofline": round(f32["over_one_step_roofline"], 4),
                      "frac_per_update": round(f32["over_one_step_roofline"], 4),
                      "one_step_kernel": one_step,
-                     "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash},
+                     "copy_reference_gbs": round(copy_gbs, 1), "kernel_hash": khash}),
         "f32": f32,
     }
     for key in ("f16_shifted", "f16_cell", "f16_moment"):

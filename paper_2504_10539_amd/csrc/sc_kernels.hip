@@ -1469,47 +1469,47 @@ void k_step2(const InstDesc* __restrict__ descs,
   two_step_march<S, NT, PF, W, false>(descs, items, nitems_p, sub, nullptr);
 }
 
-// ============================================================== three fused time steps
+// ============================================================== K fused time steps
 //
-// FP32 storage, three time steps per launch: the two-step march with one more
-// collision stage, so the populations cross HBM once per three updates.  Per
-// march position j: pull f(t) of row j + 5 and publish psi(t); collide row
-// j + 4 into the first f* ring; pull f(t + 1) of row j + 3 from it and publish
-// psi(t + 1); collide row j + 2 into the second ring; pull f(t + 2) of row
-// j + 1 from that and publish psi(t + 2); collide row j and store it.  Five
-// barriers per row, five halo rows above and below a band and five halo
-// columns on each side of a strip (W <= NT - 10).  FP32 values go through the
-// rings unrounded, so a launch is bitwise three single steps.
-constexpr int kStep3Halo = 5;
-
-template <int NT, int PF, int W>
-__device__ __forceinline__ void three_step_march(const InstDesc* __restrict__ descs,
+// FP32 storage, K >= 3 time steps per launch (the library instantiates
+// K = 3): the two-step march with more collision stages, so the populations
+// cross HBM once per K updates.
+// With H = 2K - 1 halo rows, per march position j:
+//   stage 0: pull f(t) of row j + H (loads issued PF rows ahead), publish
+//            psi(t) into psi ring 0;
+//   stage k = 1 .. K-1: collide row j + H - 2k + 1 with psi ring k - 1 into
+//            f* ring k; pull f(t + k) of row j + H - 2k from that ring and
+//            publish psi(t + k) into psi ring k;
+//   last:    collide row j with psi ring K - 1 and store it.
+// 2K - 1 barriers per row; H halo rows above and below a band and H halo
+// columns on each side of a strip (W <= NT - 2H).  Stage k's collision
+// covers ring columns [2k - 1, NT - 2k], its pull [2k, NT - 1 - 2k].  FP32
+// values go through the rings unrounded, so a launch is bitwise K single
+// steps.
+template <int NT, int PF, int W, int K>
+__device__ __forceinline__ void multi_step_march(const InstDesc* __restrict__ descs,
                                                  const TileItem* __restrict__ items,
                                                  const int* __restrict__ nitems_p, int sub) {
+  static_assert(K == 3 || K == 4, "three or four steps per launch");
   static_assert(PF == 1 || PF == 2, "one or two rows of loads in flight");
+  constexpr int H = 2 * K - 1;
   using S = StoreF32;
-  using F = Fused2<S, NT, PF, W, kStep3Halo>;
+  using F = Fused2<S, NT, PF, W, H>;
   // FP32 rows are loaded straight into the registers they are collided in:
   // a slot lives from its loads to the first collision, PF + 2 positions.
   constexpr int NR = PF + 2;
   // a multiple of NR, 2 and 3: every slot and ring index is a constant
   constexpr int U = NR == 3 ? 6 : 12;
-  static_assert(U % NR == 0, "unroll period");
-  __shared__ float psa[3][NT];  // psi(t) rows j + 3 .. j + 5
-  __shared__ float psb[3][NT];  // psi(t + 1) rows j + 1 .. j + 3
-  __shared__ float psc[3][NT];  // psi(t + 2) rows j - 1 .. j + 1
-  // f* rings (populations 0, 1, 3 of the middle row; the side row written at
-  // this position; the side row written two positions earlier), as in the
-  // two-step march: the first for rows j + 2 .. j + 4, the second for rows
-  // j .. j + 2
-  __shared__ float gmd[2][3][NT], gnew[3][NT], gold[3][3][NT];
-  __shared__ float fmd[2][3][NT], fnew[3][NT], fold[3][3][NT];
+  static_assert(U % NR == 0 && U % 6 == 0, "unroll period");
+  // psi ring k holds psi(t + k) of three consecutive rows
+  __shared__ float ps[K][3][NT];
+  // f* ring k (k = 1 .. K-1, index k - 1): populations 0, 1, 3 of the
+  // middle row (two rows), the side populations of the row collided at this
+  // position (one row) and those of the rows collided up to two positions
+  // earlier (three rows); which side is which follows the march direction
+  __shared__ float rmd[K - 1][2][3][NT], rnew[K - 1][3][NT], rold[K - 1][3][3][NT];
   const int nitems = *nitems_p;
-  const int t = strip_slot<S, NT, kStep3Halo>();
-  const bool strip_a = t >= 1 && t <= NT - 2;
-  const bool strip_b = t >= 2 && t <= NT - 3;
-  const bool strip_c = t >= 3 && t <= NT - 4;
-  const bool strip_d = t >= 4 && t <= NT - 5;
+  const int t = strip_slot<S, NT, H>();
   const int strip_f = min(max(t, 1), NT - 2);
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
@@ -1523,114 +1523,100 @@ __device__ __forceinline__ void three_step_march(const InstDesc* __restrict__ de
         const int below = upward ? 1 : -1;
         constexpr bool kW = decltype(wrap_c)::value;
         const int nx = s.nx;
-        const bool stage_a = kW ? t < nx : strip_a;
-        const bool stage_b = kW ? t < nx : strip_b;
-        const bool stage_c = kW ? t < nx : strip_c;
-        const bool stage_d = kW ? t < nx : strip_d;
+        // lanes of stage k's collision and pull (a periodic strip: every
+        // column of the grid)
+        bool col_ok[K], pull_ok[K];
+#pragma unroll
+        for (int k = 1; k < K; ++k) {
+          col_ok[k] = kW ? t < nx : (t >= 2 * k - 1 && t <= NT - 2 * k);
+          pull_ok[k] = kW ? t < nx : (t >= 2 * k && t <= NT - 1 - 2 * k);
+        }
         const int tl = kW ? (t == 0 ? nx - 1 : t - 1) : t - 1;
         const int tr = kW ? (t == nx - 1 ? 0 : min(t + 1, NT - 1)) : t + 1;
         const int tf = kW ? t : strip_f;
         const int tfl = kW ? tl : tf - 1, tfr = kW ? tr : tf + 1;
-        float fa[NR][10], fb[2][10], fc[2][10];
-        // Row R (>= -5) of the first step is loaded into slot R mod NR.
+        float fa[NR][10], fr[K - 1][2][10];
+        // Row R (>= -H) of the first step is loaded into slot R mod NR.
         auto fetch_row = [&](int row, auto slot_c) {
           s.fetch(row, fa[decltype(slot_c)::value], nullptr);
         };
         unrolled(std::make_integer_sequence<int, PF>{}, [&](auto k) {
-          fetch_row(-kStep3Halo + decltype(k)::value,
-                    std::integral_constant<int, (decltype(k)::value + kStep3Halo * NR - kStep3Halo) % NR>{});
+          fetch_row(-H + decltype(k)::value,
+                    std::integral_constant<int, (decltype(k)::value + H * NR - H) % NR>{});
         });
-        // Writes the collided row of a ring at d (its middle-row populations
-        // at slot ring2(d), the side rows as the march direction decides) and
-        // pulls row d - 1 of the same ring.
-        auto ring_put = [&](float(*md2)[3][NT], float(*nw)[NT], float(*ol3)[3][NT], int s2, int s3,
-                            const float (&g)[10]) {
-          float(*md)[NT] = md2[s2];
-          float(*old)[NT] = ol3[s3];
-          float(*dn)[NT] = upward ? nw : old;
-          float(*up)[NT] = upward ? old : nw;
-          md[0][t] = g[0];
-          md[1][t] = g[1];
-          md[2][t] = g[3];
-          dn[0][t] = g[2];
-          dn[1][t] = g[5];
-          dn[2][t] = g[6];
-          up[0][t] = g[4];
-          up[1][t] = g[7];
-          up[2][t] = g[8];
-        };
-        auto ring_pull = [&](float(*md2)[3][NT], float(*nw)[NT], float(*ol3)[3][NT], int s2, int s3,
-                             float (&f)[10]) {
-          const float(*md)[NT] = md2[s2];
-          const float(*old)[NT] = ol3[s3];
-          const float(*dn)[NT] = upward ? nw : old;
-          const float(*up)[NT] = upward ? old : nw;
-          f[0] = md[0][t];
-          f[1] = md[1][tl];
-          f[2] = dn[0][t];
-          f[3] = md[2][tr];
-          f[4] = up[0][t];
-          f[5] = dn[1][tl];
-          f[6] = dn[2][tr];
-          f[7] = up[1][tr];
-          f[8] = up[2][tl];
-          f[9] = density(f);
-        };
         auto pos = [&](auto lead_c, auto u_c, int j) {
           constexpr bool kLead = decltype(lead_c)::value;
           constexpr int u = decltype(u_c)::value;
-          constexpr int kd = (u + kStep3Halo) % NR;  // slot of row j + 5
+          // ring slots of row j + d: three-row rings (d >= -9), two-row rings
           auto ring = [&](int d) { return (u + d + 9) % 3; };
           auto ring2 = [&](int d) { return (u + d + 10) % 2; };
-          float(&fa_c)[10] = fa[kd];
-          float(&fa_p)[10] = fa[(u + 4) % NR];
-          float(&fb_c)[10] = fb[(u + 1) & 1];
-          float(&fb_p)[10] = fb[u & 1];
-          float(&fc_c)[10] = fc[(u + 1) & 1];
-          float(&fc_p)[10] = fc[u & 1];
-          fetch_row(min(j + kStep3Halo + PF, h + kStep3Halo - 1),
-                    std::integral_constant<int, (u + kStep3Halo + PF) % NR>{});
+          float(&fa_c)[10] = fa[(u + H) % NR];
+          fetch_row(min(j + H + PF, h + H - 1),
+                    std::integral_constant<int, (u + H + PF) % NR>{});
           fa_c[9] = density(fa_c);
-          psa[ring(5)][t] = psi_of(fa_c[9]);
+          ps[0][ring(H)][t] = psi_of(fa_c[9]);
           __syncthreads();
-          if ((!kLead || j >= -8) && stage_a) {  // row j + 4
-            float Fx, Fy;
-            ring_force(psa[ring(4 + below)], psa[ring(4)], psa[ring(4 - below)], t, tl, tr, s.G,
-                       Fx, Fy);
-            collide(fa_p, fa_p[9], Fx, Fy, s.tau, s.omega);
-            ring_put(gmd, gnew, gold, ring2(4), ring(4), fa_p);
-          }
-          __syncthreads();
-          if ((!kLead || j >= -6) && stage_b) {  // row j + 3 from the first ring
-            ring_pull(gmd, gnew, gold, ring2(3), ring(2), fb_c);
-            psb[ring(3)][t] = psi_of(fb_c[9]);
-          }
-          __syncthreads();
-          if ((!kLead || j >= -4) && stage_c) {  // row j + 2
-            float Fx, Fy;
-            ring_force(psb[ring(2 + below)], psb[ring(2)], psb[ring(2 - below)], t, tl, tr, s.G,
-                       Fx, Fy);
-            collide(fb_p, fb_p[9], Fx, Fy, s.tau, s.omega);
-            ring_put(fmd, fnew, fold, ring2(2), ring(2), fb_p);
-          }
-          __syncthreads();
-          if ((!kLead || j >= -2) && stage_d) {  // row j + 1 from the second ring
-            ring_pull(fmd, fnew, fold, ring2(1), ring(0), fc_c);
-            psc[ring(1)][t] = psi_of(fc_c[9]);
-          }
-          __syncthreads();
+          unrolled(std::make_integer_sequence<int, K - 1>{}, [&](auto kc) {
+            constexpr int k = decltype(kc)::value + 1;
+            constexpr int rc = H - 2 * k + 1;  // row collided at this stage
+            constexpr int rp = H - 2 * k;      // row pulled at this stage
+            float(&fp)[10] = k == 1 ? fa[(u + rc) % NR] : fr[k >= 2 ? k - 2 : 0][u & 1];
+            if ((!kLead || j >= -2 * H + 4 * k - 2) && col_ok[k]) {
+              float Fx, Fy;
+              ring_force(ps[k - 1][ring(rc + below)], ps[k - 1][ring(rc)],
+                         ps[k - 1][ring(rc - below)], t, tl, tr, s.G, Fx, Fy);
+              collide(fp, fp[9], Fx, Fy, s.tau, s.omega);
+              float(*md)[NT] = rmd[k - 1][ring2(rc)];
+              float(*old)[NT] = rold[k - 1][ring(rc)];
+              float(*dn)[NT] = upward ? rnew[k - 1] : old;
+              float(*up)[NT] = upward ? old : rnew[k - 1];
+              md[0][t] = fp[0];
+              md[1][t] = fp[1];
+              md[2][t] = fp[3];
+              dn[0][t] = fp[2];
+              dn[1][t] = fp[5];
+              dn[2][t] = fp[6];
+              up[0][t] = fp[4];
+              up[1][t] = fp[7];
+              up[2][t] = fp[8];
+            }
+            __syncthreads();
+            if ((!kLead || j >= -2 * H + 4 * k) && pull_ok[k]) {
+              // f_i(x) = f*_i(x - e_i): the middle row's rest and horizontal
+              // populations, the vertical ones from the rows collided at this
+              // position and one position earlier
+              float(&f)[10] = fr[k - 1][(u + 1) & 1];
+              const float(*md)[NT] = rmd[k - 1][ring2(rp)];
+              const float(*old)[NT] = rold[k - 1][ring(rp - 1)];
+              const float(*dn)[NT] = upward ? rnew[k - 1] : old;
+              const float(*up)[NT] = upward ? old : rnew[k - 1];
+              f[0] = md[0][t];
+              f[1] = md[1][tl];
+              f[2] = dn[0][t];
+              f[3] = md[2][tr];
+              f[4] = up[0][t];
+              f[5] = dn[1][tl];
+              f[6] = dn[2][tr];
+              f[7] = up[1][tr];
+              f[8] = up[2][tl];
+              f[9] = density(f);
+              ps[k][ring(rp)][t] = psi_of(f[9]);
+            }
+            __syncthreads();
+          });
           if constexpr (!kLead) {
+            float(&fp)[10] = fr[K - 2][u & 1];
             float Fx, Fy;
-            ring_force(psc[ring(below)], psc[ring(0)], psc[ring(-below)], tf, tfl, tfr, s.G, Fx,
-                       Fy);
-            bad |= unstable_lanes(fc_p[9], s.out);
-            collide(fc_p, fc_p[9], Fx, Fy, s.tau, s.omega);
-            s.store(j, fc_p);
+            ring_force(ps[K - 1][ring(below)], ps[K - 1][ring(0)], ps[K - 1][ring(-below)], tf,
+                       tfl, tfr, s.G, Fx, Fy);
+            bad |= unstable_lanes(fp[9], s.out);
+            collide(fp, fp[9], Fx, Fy, s.tau, s.omega);
+            s.store(j, fp);
           }
         };
-        // ten lead-in positions, j = -10 .. -1
-        unrolled(std::make_integer_sequence<int, 2 * kStep3Halo>{}, [&](auto k) {
-          constexpr int j = decltype(k)::value - 2 * kStep3Halo;
+        // 2H lead-in positions, j = -2H .. -1
+        unrolled(std::make_integer_sequence<int, 2 * H>{}, [&](auto k) {
+          constexpr int j = decltype(k)::value - 2 * H;
           pos(std::true_type{}, std::integral_constant<int, (j % U + U) % U>{}, j);
         });
         const auto phases = std::make_integer_sequence<int, U>{};
@@ -1661,7 +1647,7 @@ template <int NT, int PF, int W>
 __global__ __launch_bounds__(NT) void k_step3(const InstDesc* __restrict__ descs,
                                               const TileItem* __restrict__ items,
                                               const int* __restrict__ nitems_p, int sub) {
-  three_step_march<NT, PF, W>(descs, items, nitems_p, sub);
+  multi_step_march<NT, PF, W, 3>(descs, items, nitems_p, sub);
 }
 
 // Two steps that also record the diagnostics of the state they advance (one
@@ -2106,25 +2092,31 @@ const void* fused_fn_t() {
     return reinterpret_cast<const void*>(&k_step2<S, NT, PF, W>);
 }
 
-// Three-step kernels: FP32 storage only.
-template <class S, int NT, int PF, int W>
-hipError_t launch_step3_t(const InstDesc* descs, const TileItem* items, const int* nitems,
+// Kernels of more than two steps per launch: FP32 storage only.
+template <int K, int NT, int PF, int W>
+constexpr auto multi_kernel() {
+  static_assert(K == 3, "three steps per launch");
+  return &k_step3<NT, PF, W>;
+}
+
+template <class S, int K, int NT, int PF, int W>
+hipError_t launch_multi_t(const InstDesc* descs, const TileItem* items, const int* nitems,
                           int grid, int sub, hipStream_t st) {
   if constexpr (!std::is_same<S, StoreF32>::value) {
     return hipErrorInvalidDeviceFunction;
   } else {
-    hipLaunchKernelGGL((k_step3<NT, PF, W>), dim3(grid), dim3(NT), 0, st, descs, items, nitems,
-                       sub);
+    constexpr auto kern = multi_kernel<K, NT, PF, W>();
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, st, descs, items, nitems, sub);
     return hipGetLastError();
   }
 }
 
-template <class S, int NT, int PF, int W>
-const void* step3_fn_t() {
+template <class S, int K, int NT, int PF, int W>
+const void* multi_fn_t() {
   if constexpr (!std::is_same<S, StoreF32>::value)
     return nullptr;
   else
-    return reinterpret_cast<const void*>(&k_step3<NT, PF, W>);
+    return reinterpret_cast<const void*>(multi_kernel<K, NT, PF, W>());
 }
 
 template <class S, int NW, int PF>
@@ -2170,7 +2162,7 @@ using StepFn = const void* (*)();
 
 // Three-step variants (FP32): strips of a multiple of 16 columns with five
 // halo columns on each side.
-#define SCLBM_STEP3_VARIANTS(X) X(128, 1, 112) X(256, 1, 240) X(256, 2, 240) X(512, 1, 496)
+#define SCLBM_MULTI_VARIANTS(X) X(3, 128, 1, 112) X(3, 256, 1, 240) X(3, 256, 2, 240) X(3, 512, 1, 496)
 
 #define SCLBM_AS_VARIANT(NT, CPT, PF) StepVariant{NT, CPT, PF, 0, 1, 0},
 #define SCLBM_AS_LAUNCH(NT, CPT, PF) launch_step_t<S, NT, CPT, PF>,
@@ -2181,20 +2173,20 @@ using StepFn = const void* (*)();
 #define SCLBM_FUSED_AS_VARIANT(NT, PF, W) StepVariant{NT, 1, PF, 0, 2, W},
 #define SCLBM_FUSED_AS_LAUNCH(NT, PF, W) launch_fused_t<S, NT, PF, W>,
 #define SCLBM_FUSED_AS_FN(NT, PF, W) fused_fn_t<S, NT, PF, W>,
-#define SCLBM_STEP3_AS_VARIANT(NT, PF, W) StepVariant{NT, 1, PF, 0, 3, W},
-#define SCLBM_STEP3_AS_LAUNCH(NT, PF, W) launch_step3_t<S, NT, PF, W>,
-#define SCLBM_STEP3_AS_FN(NT, PF, W) step3_fn_t<S, NT, PF, W>,
+#define SCLBM_MULTI_AS_VARIANT(K, NT, PF, W) StepVariant{NT, 1, PF, 0, K, W},
+#define SCLBM_MULTI_AS_LAUNCH(K, NT, PF, W) launch_multi_t<S, K, NT, PF, W>,
+#define SCLBM_MULTI_AS_FN(K, NT, PF, W) multi_fn_t<S, K, NT, PF, W>,
 constexpr StepVariant kVariants[] = {
     SCLBM_STEP_VARIANTS(SCLBM_AS_VARIANT) SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_VARIANT)
-        SCLBM_FUSED_VARIANTS(SCLBM_FUSED_AS_VARIANT) SCLBM_STEP3_VARIANTS(SCLBM_STEP3_AS_VARIANT)};
+        SCLBM_FUSED_VARIANTS(SCLBM_FUSED_AS_VARIANT) SCLBM_MULTI_VARIANTS(SCLBM_MULTI_AS_VARIANT)};
 template <class S>
 constexpr StepLauncher kLaunch[] = {
     SCLBM_STEP_VARIANTS(SCLBM_AS_LAUNCH) SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_LAUNCH)
-        SCLBM_FUSED_VARIANTS(SCLBM_FUSED_AS_LAUNCH) SCLBM_STEP3_VARIANTS(SCLBM_STEP3_AS_LAUNCH)};
+        SCLBM_FUSED_VARIANTS(SCLBM_FUSED_AS_LAUNCH) SCLBM_MULTI_VARIANTS(SCLBM_MULTI_AS_LAUNCH)};
 template <class S>
 constexpr StepFn kFn[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_FN) SCLBM_PAIR_VARIANTS(SCLBM_PAIR_AS_FN)
                               SCLBM_FUSED_VARIANTS(SCLBM_FUSED_AS_FN)
-                                  SCLBM_STEP3_VARIANTS(SCLBM_STEP3_AS_FN)};
+                                  SCLBM_MULTI_VARIANTS(SCLBM_MULTI_AS_FN)};
 #undef SCLBM_AS_VARIANT
 #undef SCLBM_AS_LAUNCH
 #undef SCLBM_AS_FN
@@ -2204,9 +2196,9 @@ constexpr StepFn kFn[] = {SCLBM_STEP_VARIANTS(SCLBM_AS_FN) SCLBM_PAIR_VARIANTS(S
 #undef SCLBM_FUSED_AS_VARIANT
 #undef SCLBM_FUSED_AS_LAUNCH
 #undef SCLBM_FUSED_AS_FN
-#undef SCLBM_STEP3_AS_VARIANT
-#undef SCLBM_STEP3_AS_LAUNCH
-#undef SCLBM_STEP3_AS_FN
+#undef SCLBM_MULTI_AS_VARIANT
+#undef SCLBM_MULTI_AS_LAUNCH
+#undef SCLBM_MULTI_AS_FN
 
 static_assert(sizeof(kVariants) / sizeof(kVariants[0]) == kNumVariants, "variant table");
 

@@ -784,9 +784,9 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
       widest = c;
     }
   if (best < 0) return best;
-  // a three-step member tile: the two-step variant of the same strips
+  // a member tile of three or four steps: the two-step variant of the same strips
   const StepVariant& bv = step_variant(best);
-  if (bv.steps == 3) best = find_variant(bv.threads, 1, bv.prefetch, 0, 2, bv.width);
+  if (bv.steps >= 3) best = find_variant(bv.threads, 1, bv.prefetch, 0, 2, bv.width);
   for (lbm_ctx* c : m)
     if (c->p.storage == storage && !tile_batchable(best * kNumRows, c->p.nx, storage))
       return tile_variant(default_strip_tile(widest->p));

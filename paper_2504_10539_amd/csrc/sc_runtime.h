@@ -82,7 +82,7 @@ inline int find_variant(int threads, int cells, int prefetch, int paired, int st
 // halo columns on each side; three-step shapes: FP32 only).
 inline bool tile_valid(int k, int nx, int storage) {
   const StepVariant& v = step_variant(tile_variant(k));
-  if (v.steps == 3 && storage != LBM_F32) return false;
+  if (v.steps >= 3 && storage != LBM_F32) return false;
   if (storage == LBM_F16_MOMENT && (v.paired || (v.steps == 2 && v.width > v.threads - 8)))
     return false;
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);

@@ -111,9 +111,9 @@ def test_tile_table(lbm):
                                      None, None) == lbm.LBM_EINVAL
     for t in tiles:
         assert t["steps"] in (1, 2, 3)
-        if t["steps"] == 3:  # five halo columns on each side, 64-byte-aligned FP32 strips
+        if t["steps"] >= 3:  # 2K - 1 halo columns on each side, 64-byte-aligned FP32 strips
             assert not t["paired"] and t["cells"] == 1
-            assert t["width"] <= t["threads"] - 10 and t["width"] % 16 == 0
+            assert t["width"] <= t["threads"] - 2 * (2 * t["steps"] - 1) and t["width"] % 16 == 0
         elif t["steps"] == 2:  # three halo columns on each side of the strip
             assert not t["paired"] and t["cells"] == 1
             assert t["width"] == t["threads"] - 6 or (t["width"] < t["threads"] - 6
@@ -122,7 +122,7 @@ def test_tile_table(lbm):
             assert t["cells"] == 2 and t["width"] == t["threads"] // 64 * 124
         else:
             assert t["width"] == t["threads"] * t["cells"]
-    assert any(t["steps"] == 2 for t in tiles) and any(t["steps"] == 3 for t in tiles)
+    assert {t["steps"] for t in tiles} == {1, 2, 3}
 
 
 def test_tile_layout(lbm):

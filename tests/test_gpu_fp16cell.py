@@ -179,7 +179,7 @@ def test_fp16_cell_tile_shapes_bitwise_identical():
     f0 = f32_state(oracle.droplet_state(nx, ny, [(150.0, 38.0, 20.0), (20.0, 70.0, 9.0)], seed=6))
     ref = None
     for t in L.tiles():
-        if t["steps"] == 3:  # FP32 only
+        if t["steps"] >= 3:  # FP32 only
             continue
         sim = L.Simulation(nx, ny, -5.5, 0.8, L.LBM_F16_CELL)
         sim.set_tile(t["id"])

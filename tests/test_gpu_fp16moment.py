@@ -211,7 +211,7 @@ def test_moment_tile_shapes_bitwise_identical():
     ref = None
     sim = L.Simulation(nx, ny, -5.5, 0.8, L.LBM_F16_MOMENT)
     for t in L.tiles():
-        if t["paired"] or t["steps"] == 3 or (t["steps"] == 2 and t["width"] > t["threads"] - 8):
+        if t["paired"] or t["steps"] >= 3 or (t["steps"] == 2 and t["width"] > t["threads"] - 8):
             with pytest.raises(L.LbmError) as e:
                 sim.set_tile(t["id"])
             assert e.value.code == L.LBM_EINVAL

@@ -1,12 +1,14 @@
-"""Three-step tile shapes (FP32): one launch advances its strip by three time
-steps, the two intermediate post-collision states kept on chip.
+"""Three-step tile shapes (FP32): one launch advances its strip by K = 3 time
+steps, the intermediate post-collision states kept on chip.
 
-Bar: every three-step shape reproduces the single-step path bitwise (ragged
-and degenerate grids, step counts that are not multiples of three, split over
-calls) and the FP64 oracle to FP32 rounding; a metric series and a batch are
-unchanged by a run's three-step tile.  Method: Li & Zhang, arXiv 2504.10539,
+Bar: every such shape reproduces the single-step path bitwise (ragged and
+degenerate grids, step counts that are not multiples of K, split over calls)
+and the FP64 oracle to FP32 rounding; a metric series and a batch are
+unchanged by a run's K-step tile.  Method: Li & Zhang, arXiv 2504.10539,
 Sec. II-A Eq. (1).
 """
+import itertools
+
 import numpy as np
 import pytest
 
@@ -22,8 +24,8 @@ def _gpu():
     need_gpu()
 
 
-def _three_step(rows=None):
-    return [t for t in lbm().tiles() if t["steps"] == 3 and (rows is None or t["rows"] in rows)]
+def _multi_step(rows=None, steps=(3,)):
+    return [t for t in lbm().tiles() if t["steps"] in steps and (rows is None or t["rows"] in rows)]
 
 
 def _strip_tile():
@@ -35,46 +37,48 @@ def _strip_tile():
 @pytest.mark.parametrize("nx,ny", [(1, 1), (2, 5), (5, 3), (7, 4), (40, 9), (117, 6), (128, 4),
                                    (240, 2), (241, 13), (245, 3), (246, 6), (256, 7), (300, 77),
                                    (512, 3), (513, 5)])
-def test_three_step_shapes_match_single_step(nx, ny):
+def test_multi_step_shapes_match_single_step(nx, ny):
     """Strips narrower than the halo, short and one-row bands, widths around
     the strip and workgroup widths (grids up to the workgroup's width run as
-    one periodic strip); 8 steps as 1 + 7 (one single step, two three-step
-    launches and a single step)."""
+    one periodic strip); 11 steps as 1 + 10 (three launches and a single
+    step)."""
     L = lbm()
     f0 = f32_state(inputs.random_positive_state(nx, ny, seed=nx * 11 + ny))
     ref = L.Simulation(nx, ny, -5.5, 0.8)
     ref.set_tile(_strip_tile())
     set_state_from(ref, f0)
-    ref.step(8)
+    ref.step(11)
     want = to_np(ref.get_state())
-    for t in _three_step(rows=(2, 8, 128)):
+    for t in _multi_step(rows=(2, 8, 128)):
         s = L.Simulation(nx, ny, -5.5, 0.8)
         s.set_tile(t["id"])
         set_state_from(s, f0)
         s.step(1)
-        s.step(7)
-        assert s.steps == 8
+        s.step(10)
+        assert s.steps == 11
         got = to_np(s.get_state())
         assert np.array_equal(got, want), (t, nx, ny)
         s.close()
 
 
-def test_three_step_refused_by_fp16_storage():
+def test_multi_step_refused_by_fp16_storage():
     L = lbm()
-    t = _three_step()[0]
-    for st in (L.LBM_F16_SHIFTED, L.LBM_F16_CELL, L.LBM_F16_MOMENT):
+    for t, st in itertools.product(_multi_step(rows=(8,)),
+                                   (L.LBM_F16_SHIFTED, L.LBM_F16_CELL, L.LBM_F16_MOMENT)):
         s = L.Simulation(64, 64, -5.0, 1.0, st, 1.0 if st == L.LBM_F16_SHIFTED else 0.0)
         with pytest.raises(L.LbmError) as e:
             s.set_tile(t["id"])
         assert e.value.code == L.LBM_EINVAL
 
 
-def test_three_step_droplet_meets_oracle():
-    """A droplet run with the balanced three-step shape against the FP64 oracle."""
+@pytest.mark.parametrize("k", [3])
+def test_multi_step_droplet_meets_oracle(k):
+    """A droplet run with the balanced K-step shape against the FP64 oracle."""
     L = lbm()
     N = 96
     drops = inputs.single_droplet(N, 20)
-    bal = next(t for t in _three_step() if t["threads"] == 256 and t["prefetch"] == 1 and t["rows"] == 0)
+    bal = next(t for t in _multi_step(steps=(k,)) if t["threads"] == 256 and t["prefetch"] == 1
+               and t["rows"] == 0)
     s = L.Simulation(N, N, -5.0, 1.0).init_droplets(drops, seed=1)
     s.set_tile(bal["id"])
     s.step(300)
@@ -84,12 +88,13 @@ def test_three_step_droplet_meets_oracle():
     assert float(np.max(np.abs(rho - rho_ref) / rho_ref)) < 1e-5
 
 
-def test_series_with_three_step_tile_is_unchanged():
+@pytest.mark.parametrize("k", [3])
+def test_series_with_multi_step_tile_is_unchanged(k):
     L = lbm()
     nx, ny = 200, 90
     drops = [(80.0, 45.0, 20.0), (170.0, 20.0, 9.0)]
     runs = []
-    for tile in (_strip_tile(), _three_step(rows=(8,))[1]["id"]):
+    for tile in (_strip_tile(), _multi_step(rows=(8,), steps=(k,))[1]["id"]):
         s = L.Simulation(nx, ny, -5.5, 1.0).init_droplets(drops, seed=2)
         s.set_tile(tile)
         recs = s.step_series(25, 4)
@@ -100,17 +105,18 @@ def test_series_with_three_step_tile_is_unchanged():
     assert ra == rb
 
 
-def test_batch_member_with_three_step_tile():
-    """A batch takes one or two steps per launch: a member with a three-step
-    tile runs the two-step shape of the same strips, bitwise as alone."""
+@pytest.mark.parametrize("k", [3])
+def test_batch_member_with_multi_step_tile(k):
+    """A batch takes one or two steps per launch: a member with a K-step tile
+    runs the two-step shape of the same strips, bitwise as alone."""
     L = lbm()
     mk = [lambda: L.Simulation(120, 64, -5.0, 1.0).init_droplets([(50, 30, 14)], seed=5),
           lambda: L.Simulation(96, 96, -5.5, 0.9).init_droplets([(40, 40, 15)], seed=6)]
-    three = _three_step(rows=(8,))[1]["id"]
+    multi = _multi_step(rows=(8,), steps=(k,))[1]["id"]
     batch = [m() for m in mk]
     solo = [m() for m in mk]
     for s in batch:
-        s.set_tile(three)
+        s.set_tile(multi)
     bt = L.Batch(batch, steps_per_graph=8)
     bt.step(13)
     for s in solo:

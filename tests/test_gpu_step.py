@@ -149,7 +149,7 @@ def test_tile_shapes_bitwise_identical(storage):
     f0 = f32_state(oracle.droplet_state(nx, ny, [(150.0, 38.0, 20.0), (20.0, 70.0, 9.0)], seed=6))
     ref = None
     for t in lbm().tiles():
-        if t["steps"] == 3 and storage != 0:
+        if t["steps"] >= 3 and storage != 0:
             continue
         sim = _sim(nx, ny, -5.5, 0.8, storage, 1.0 if storage else 0.0)
         sim.set_tile(t["id"])
