@@ -604,7 +604,8 @@ def main():
     ap.add_argument("--c2-steps", type=int, default=10000)
     ap.add_argument("--pinn-steps", type=int, default=500)
     ap.add_argument("--pinn-epochs", type=int, default=300)
-    ap.add_argument("--only", choices=["single_droplet_1024", "serving", "pinn"], default=None,
+    ap.add_argument("--only", choices=["single_droplet_1024", "serving", "pinn", "sweep"],
+                    default=None,
                     help="run one extra workload alone and print its result (for profiling)")
     ap.add_argument("--graph-steps", type=int, default=32)
     ap.add_argument("--sweep-instances", type=int, default=512)
@@ -643,6 +644,9 @@ def main():
         return
     if args.only == "pinn":
         print(json.dumps(run_pinn(args, torch, lbm, inputs)), flush=True)
+        return
+    if args.only == "sweep":
+        print(json.dumps(run_sweep(args, torch, lbm, inputs)), flush=True)
         return
     log(f"device {torch.cuda.get_device_name(0)}; workload {args.n}^2, {args.drops} droplets, "
         f"G {args.G}, tau {args.tau}, {args.lbm_steps} LBM steps per job")

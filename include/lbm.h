@@ -165,8 +165,10 @@ lbm_status lbm_destroy(lbm_ctx* ctx);
 lbm_status lbm_init_droplets(lbm_ctx* ctx, const double* drops, int32_t n, const lbm_init* ip);
 
 /* Enqueues n >= 0 time steps (Eq. (1)): one fused pull-stream, force and
- * collide kernel launch per step (per two steps with a two-step tile shape,
- * plus one single-step launch when n is odd), alternating the two buffers.
+ * collide kernel launch per step, per two steps with a two-step tile shape
+ * (plus one single-step launch when n is odd) or per three with a three-step
+ * shape (plus one two-step or one single-step launch for the steps left
+ * over), alternating the two buffers.
  * Returns after enqueue.  LBM_EBUSY if the context belongs to a live batch. */
 lbm_status lbm_step_n(lbm_ctx* ctx, int64_t n);
 
@@ -243,13 +245,16 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * round them); such a strip reads three halo columns on each side of its
  * `width`, which is threads - 6 or a multiple of 16 below that (strips that
  * start and end on 64-byte boundaries in FP32), and a grid no wider than
- * `threads` is marched as one periodic strip with no halo columns.  rows = 0:
+ * `threads` is marched as one periodic strip with no halo columns.  steps =
+ * 3 (LBM_F32 only): the same over three time steps, five halo columns on
+ * each side (`width` a multiple of 16, at most threads - 10).  rows = 0:
  * balanced bands, whose height is chosen per grid so that a launch is about
  * two rounds of the workgroups the device holds at once (lbm_tile_layout
- * gives it).  LBM_F16_MOMENT runs strip shapes (steps = 1, paired = 0) only:
- * lbm_set_tile refuses the others for it with LBM_EINVAL.  Every valid shape
- * computes bitwise the same result; only speed differs.  Any output pointer may be NULL; k out of range
- * is LBM_EINVAL. */
+ * gives it).  LBM_F16_MOMENT runs strip shapes (steps = 1, paired = 0) and
+ * two-step shapes of at most threads - 8 columns; lbm_set_tile refuses the
+ * shapes a storage type does not run with LBM_EINVAL.  Every valid shape
+ * computes bitwise the same result; only speed differs.  Any output pointer
+ * may be NULL; k out of range is LBM_EINVAL. */
 int32_t lbm_tile_count(void);
 lbm_status lbm_tile_describe(int32_t k, int32_t* width, int32_t* rows, int32_t* threads,
                              int32_t* prefetch, int32_t* cells, int32_t* paired, int32_t* steps);

@@ -33,7 +33,7 @@ struct InstDesc {
   int64_t remaining;  // batched runs: steps still to take
   int64_t steps;      // batched runs: steps taken
   int32_t storage;
-  int32_t two_step;   // batched runs: advanced by two-step launches (and a tail)
+  int32_t per_launch;  // batched runs: steps per launch of the batch's step kernel (1, 2, 3)
   // Address of a 32-bit status word that a step kernel sets to 1 when it
   // meets a cell whose density is not finite or not positive (0: no word).
   // The serving loop points it at pinned host memory and retires such a run
@@ -42,23 +42,41 @@ struct InstDesc {
 };
 static_assert(sizeof(InstDesc) == 80, "InstDesc layout");
 
-constexpr int kTailSub = -1;
+constexpr int kTailSub = -1;   // the single step after a tick's multi-step launches
+constexpr int kTail2Sub = -2;  // the two steps after a tick's three-step launches
 
+// Steps per launch of the batch step kernel this simulation runs under (1
+// outside batches).
+__host__ __device__ __forceinline__ int launch_steps(const InstDesc* d) {
+  return d->per_launch > 1 ? d->per_launch : 1;
+}
 // Whether single-step launch `sub` runs for this simulation, and the buffer
-// it reads (the tail launch follows the nsub / 2 two-step launches).
+// it reads: the sub-th launch of a single-step tick, or (kTailSub) the last
+// step of a tick of nsub / K multi-step launches when nsub mod K is 1.
 __host__ __device__ __forceinline__ bool step_runs(const InstDesc* d, int sub) {
-  return sub >= 0 ? sub < d->nsub : (d->nsub & 1) != 0;
+  return sub >= 0 ? sub < d->nsub : d->nsub % launch_steps(d) == 1;
 }
 __host__ __device__ __forceinline__ int step_parity(const InstDesc* d, int sub) {
-  return (d->parity + (sub >= 0 ? sub : d->nsub >> 1)) & 1;
+  return (d->parity + (sub >= 0 ? sub : d->nsub / launch_steps(d))) & 1;
 }
-// Whether two-step launch `sub` runs (it reads pop[(parity + sub) & 1]).
+// Whether two-step launch `sub` runs: the sub-th launch of a two-step tick,
+// or (kTail2Sub) the last two steps of a tick of three-step launches.
 __host__ __device__ __forceinline__ bool pair_runs(const InstDesc* d, int sub) {
-  return sub < (d->nsub >> 1);
+  return sub >= 0 ? sub < (d->nsub >> 1) : d->nsub % 3 == 2;
 }
-// Buffer swaps of a tick of n steps: one per launch.
-__host__ __device__ __forceinline__ int64_t tick_flips(int64_t n, bool two_step) {
-  return two_step ? (n >> 1) + (n & 1) : n;
+// The buffer a two- or three-step launch reads: pop[(parity + sub) & 1], or
+// for the two-step tail the one the nsub / 3 three-step launches left.
+__host__ __device__ __forceinline__ int pair_parity(const InstDesc* d, int sub) {
+  return (d->parity + (sub >= 0 ? sub : d->nsub / 3)) & 1;
+}
+// Whether launch `sub` of a tick of k-step launches (k >= 3) runs.
+__host__ __device__ __forceinline__ bool multi_runs(const InstDesc* d, int sub, int k) {
+  return sub < d->nsub / k;
+}
+// Buffer swaps of a tick of n steps with K-step launches: one per launch,
+// the steps left over in one further launch.
+__host__ __device__ __forceinline__ int64_t tick_flips(int64_t n, int k) {
+  return k == 3 ? n / 3 + (n % 3 != 0) : (k == 2 ? (n >> 1) + (n & 1) : n);
 }
 
 // One unit of step-kernel work: rows [y0, y0 + h) of the strip of columns

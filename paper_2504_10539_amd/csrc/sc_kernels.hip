@@ -976,7 +976,7 @@ struct Fused2 {
     tau = dp->tau;
     omega = dp->omega;
     const float rho0 = dp->rho0;
-    const int par = (dp->parity + sub) & 1;  // sub >= 0
+    const int par = pair_parity(dp, sub);
     const uint64_t a = dp->pop[0], b = dp->pop[1];
     src = par ? b : a;
     dst = par ? a : b;
@@ -1514,7 +1514,7 @@ __device__ __forceinline__ void multi_step_march(const InstDesc* __restrict__ de
   for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
     const TileItem ti = items[__builtin_amdgcn_readfirstlane(it)];
     const InstDesc* __restrict__ dp = descs + __builtin_amdgcn_readfirstlane(ti.inst);
-    if (pair_runs(dp, sub)) {
+    if (multi_runs(dp, sub, K)) {
       F s;
       s.setup(dp, ti, sub);
       const int h = s.h;
@@ -1689,7 +1689,7 @@ __global__ void k_tick_end(InstDesc* descs, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     const int32_t s = descs[i].nsub;
-    descs[i].parity = (int32_t)((descs[i].parity + tick_flips(s, descs[i].two_step != 0)) & 1);
+    descs[i].parity = (int32_t)((descs[i].parity + tick_flips(s, launch_steps(descs + i))) & 1);
     descs[i].remaining -= s;
     descs[i].steps += s;
     descs[i].nsub = 0;

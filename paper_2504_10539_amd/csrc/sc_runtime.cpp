@@ -456,6 +456,17 @@ lbm_status lbm_ctx::advance(int64_t n) {
     parity ^= 1;
     steps += per;
   }
+  if (n >= 2) {
+    // two steps left after three-step launches: the two-step variant of the
+    // same strips, over the same work items
+    const StepVariant& tv = step_variant(v);
+    const int v2 = find_variant(tv.threads, 1, tv.prefetch, 0, 2, tv.width);
+    if (v2 < 0) return fail(LBM_EDEVICE, "no two-step variant for a three-step tile");
+    SCLBM_HIP(launch_step(p.storage, v2, d_desc, d_items, d_nitems, nitems, parity, stream));
+    parity ^= 1;
+    steps += 2;
+    n -= 2;
+  }
   if (n > 0) {
     const lbm_status s = series_tiles();
     if (s != LBM_OK) return s;
@@ -545,7 +556,13 @@ size_t BatchEngine::work_bytes(int cap_inst, const int cap_items[kNumStorages],
 }
 
 int tail_variant_for(int variant) {
-  return step_variant(variant).steps == 2 ? find_variant(kSeriesThreads, 1, 2, 0) : -1;
+  return step_variant(variant).steps >= 2 ? find_variant(kSeriesThreads, 1, 2, 0) : -1;
+}
+
+// Two-step variant of the same strips as three-step variant v (-1 for others).
+static int pair_variant_for(int v) {
+  const StepVariant& sv = step_variant(v);
+  return sv.steps == 3 ? find_variant(sv.threads, 1, sv.prefetch, 0, 2, sv.width) : -1;
 }
 
 lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
@@ -581,7 +598,7 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
     o += align_up((size_t)cap_items[s] * sizeof(TileItem), 256);
     grid[s] = tgrid[s] = 0;
     cap_titems[s] = cap_titems_[s];
-    tail_variant[s] = -1;
+    tail_variant[s] = pair_variant[s] = -1;
     if (cap_titems[s] > 0) {
       d_tnitems[s] = reinterpret_cast<int*>(w + o);
       o += 256;
@@ -591,10 +608,16 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
     if (variant[s] < 0 || cap_items[s] == 0) continue;
     lbm_status r = grid_for(s, variant[s], cap_items[s], &grid[s]);
     if (r != LBM_OK) return r;
-    if (two_step(s)) {
-      if (cap_titems[s] == 0) return fail(LBM_EINVAL, "two-step batch without a tail table");
+    if (per_launch(s) >= 2) {
+      if (cap_titems[s] == 0) return fail(LBM_EINVAL, "multi-step batch without a tail table");
       tail_variant[s] = tail_variant_for(variant[s]);
       r = grid_for(s, tail_variant[s], cap_titems[s], &tgrid[s]);
+      if (r != LBM_OK) return r;
+    }
+    if (per_launch(s) == 3) {
+      pair_variant[s] = pair_variant_for(variant[s]);
+      if (pair_variant[s] < 0) return fail(LBM_EINVAL, "no two-step variant for a three-step batch");
+      r = grid_for(s, pair_variant[s], cap_items[s], &p2grid[s]);
       if (r != LBM_OK) return r;
     }
   }
@@ -615,13 +638,15 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
   for (int b = 0; b < 2; ++b)
     SCLBM_HIP(hipEventCreateWithFlags(&staged[b], hipEventDisableTiming));
   // Graph: tick_begin -> the step launches of every storage type (K single
-  // steps, or ceil(K / 2) two-step launches and a tail) -> tick_end.
+  // steps; ceil(K / 2) two-step launches and a tail; or floor(K / 3)
+  // three-step launches and two tails) -> tick_end.
   SCLBM_HIP(hipGraphCreate(&graph, 0));
   hipGraphNode_t prev;
   SCLBM_HIP(graph_add_tick(graph, &prev, nullptr, 0, true, d_desc, cap_inst, K));
   int launches[kNumStorages], most = 0;
   for (int s = 0; s < kNumStorages; ++s) {
-    launches[s] = grid[s] == 0 ? 0 : (two_step(s) ? (K + 1) / 2 : K);
+    const int per = per_launch(s);
+    launches[s] = grid[s] == 0 ? 0 : (per == 3 ? K / 3 : (per == 2 ? (K + 1) / 2 : K));
     most = std::max(most, launches[s]);
   }
   for (int j = 0; j < most; ++j)
@@ -634,7 +659,15 @@ lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
       prev = node;
     }
   for (int s = 0; s < kNumStorages; ++s) {
-    if (grid[s] == 0 || !two_step(s)) continue;
+    if (grid[s] == 0 || per_launch(s) != 3) continue;
+    hipGraphNode_t node;
+    SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, pair_variant[s], d_desc, d_items[s],
+                             d_nitems[s], p2grid[s], kTail2Sub));
+    step_nodes[s].push_back(node);
+    prev = node;
+  }
+  for (int s = 0; s < kNumStorages; ++s) {
+    if (grid[s] == 0 || per_launch(s) < 2) continue;
     hipGraphNode_t node;
     SCLBM_HIP(graph_add_step(graph, &node, &prev, 1, s, tail_variant[s], d_desc, d_titems[s],
                              d_tnitems[s], tgrid[s], kTailSub));
@@ -674,7 +707,7 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
       d.steps = c->steps;
       const int s = c->p.storage;
       if (grid[s] == 0) return fail(LBM_EINVAL, "batch has no kernel for this storage type");
-      d.two_step = two_step(s) ? 1 : 0;
+      d.per_launch = per_launch(s);
       const int k = member_tile(c, variant[s], tile_override, row_override);
       std::vector<TileItem> items;
       make_items(c->p.nx, c->p.ny, s, k, i, items);
@@ -682,7 +715,7 @@ lbm_status BatchEngine::load(const std::vector<lbm_ctx*>& m, const std::vector<i
         return fail(LBM_ENOMEM, "batch tile table full");
       std::copy(items.begin(), items.end(), h_items[s][sb] + count[s]);
       count[s] += (int)items.size();
-      if (d.two_step) {  // the tail launch's items: same band height
+      if (d.per_launch >= 2) {  // the tail launch's items: same band height
         items.clear();
         make_items(c->p.nx, c->p.ny, s, tail_variant[s] * kNumRows + k % kNumRows, i, items);
         if (tcount[s] + (int)items.size() > cap_titems[s])
@@ -784,9 +817,6 @@ int pick_variant(const std::vector<lbm_ctx*>& m, int storage) {
       widest = c;
     }
   if (best < 0) return best;
-  // a member tile of three or four steps: the two-step variant of the same strips
-  const StepVariant& bv = step_variant(best);
-  if (bv.steps >= 3) best = find_variant(bv.threads, 1, bv.prefetch, 0, 2, bv.width);
   for (lbm_ctx* c : m)
     if (c->p.storage == storage && !tile_batchable(best * kNumRows, c->p.nx, storage))
       return tile_variant(default_strip_tile(widest->p));
@@ -832,7 +862,7 @@ BatchShape batch_shape(const std::vector<lbm_ctx*>& m, int tile_override = -1) {
     if (b.variants[s] >= 0 && tile_override >= 0) b.variants[s] = tile_variant(tile_override);
     const bool used = b.variants[s] >= 0;
     b.items[s] = used ? count_items(m, s, b.variants[s], tile_override) : 0;
-    b.titems[s] = used && step_variant(b.variants[s]).steps == 2
+    b.titems[s] = used && step_variant(b.variants[s]).steps >= 2
                       ? count_items(m, s, b.variants[s], tile_override, true)
                       : 0;
   }
@@ -1139,9 +1169,11 @@ lbm_status lbm_set_tile(lbm_ctx* c, int32_t k) {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (k < 0 || k >= kNumTiles) return fail(LBM_EINVAL, "tile index out of range");
     if (!tile_valid(k, c->p.nx, c->p.storage))
-      return fail(LBM_EINVAL, c->p.storage == LBM_F16_MOMENT
-                                  ? "moment storage runs strip shapes and two-step shapes of at most threads - 8 columns"
-                                  : "paired-column tile shapes need an even nx >= 128");
+      return fail(LBM_EINVAL,
+                  c->p.storage == LBM_F16_MOMENT
+                      ? "moment storage runs strip shapes and two-step shapes of at most threads - 8 columns"
+                  : tile_steps(k) >= 3 ? "three-step tile shapes take FP32 storage only"
+                                       : "paired-column tile shapes need an even nx >= 128");
     if (c->batch) return fail(LBM_EBUSY, "context is a member of a live batch");
     return c->upload_tile(k);
   });
@@ -1305,8 +1337,8 @@ lbm_status lbm_batch_step_n(lbm_batch* b, int64_t n) {
     if (st != LBM_OK) return st;
     const int64_t K = b->eng.K;
     for (lbm_ctx* c : b->members) {
-      const bool two = b->eng.two_step(c->p.storage);
-      const int64_t flips = (n / K) * tick_flips(K, two) + tick_flips(n % K, two);
+      const int per = b->eng.per_launch(c->p.storage);
+      const int64_t flips = (n / K) * tick_flips(K, per) + tick_flips(n % K, per);
       c->steps += n;
       c->parity = (int)((c->parity + flips) & 1);
     }
@@ -1328,7 +1360,7 @@ lbm_status lbm_batch_autotune(lbm_batch* b, int32_t reps, int32_t* best_out) {
       bool valid = true;
       for (lbm_ctx* c : b->members) valid = valid && tile_batchable(k, c->p.nx, c->p.storage);
       if (!valid) continue;
-      // Every member takes one step (two with a two-step shape) per launch from
+      // Every member takes one launch (of one, two or three steps) from
       // its current buffer into its idle one, and the descriptors are not
       // advanced: the state is unchanged.  Compared per time step.
       const int per = tile_steps(k);

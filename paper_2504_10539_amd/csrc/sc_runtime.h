@@ -87,11 +87,9 @@ inline bool tile_valid(int k, int nx, int storage) {
     return false;
   return !v.paired || (nx % 2 == 0 && nx >= kPairMinNx);
 }
-// Whether a batch can use tile shape k (batches take one or two steps per
-// launch).
-inline bool tile_batchable(int k, int nx, int storage) {
-  return tile_steps(k) <= 2 && tile_valid(k, nx, storage);
-}
+// Whether a batch can use tile shape k (every shape a run of this storage
+// type can use: batches take one, two or three steps per launch).
+inline bool tile_batchable(int k, int nx, int storage) { return tile_valid(k, nx, storage); }
 
 // Band height tile shape k uses on an nx x ny grid of this storage type
 // (balanced shapes: from the step kernel's occupancy on the current device).
@@ -126,20 +124,25 @@ int device_cu_count();
 
 // Multi-simulation stepping: a device descriptor table and one tile table per
 // storage type, advanced by a HIP graph of persistent step launches between a
-// tick-begin and a tick-end kernel: K single-step launches per storage type,
-// or, for a two-step variant, ceil(K / 2) two-step launches and one
-// single-step tail launch (its own tile table, tail_variant) that takes the
-// last step of members with an odd step count this tick.  The graph reads the
-// tables from device memory, so members can change between replays without
-// rebuilding it.
+// tick-begin and a tick-end kernel: K single-step launches per storage type;
+// for a two-step variant, ceil(K / 2) two-step launches and one single-step
+// tail launch (its own tile table, tail_variant) that takes the last step of
+// members with an odd step count this tick; for a three-step variant,
+// floor(K / 3) three-step launches, a two-step tail launch over the same
+// items (pair_variant, the two-step variant of the same strips) for members
+// with two steps left over, and the single-step tail for those with one.  The
+// graph reads the tables from device memory, so members can change between
+// replays without rebuilding it.
 struct BatchEngine {
   hipStream_t stream = nullptr;
   int K = 1, cap_inst = 0;
   int cap_items[kNumStorages] = {}, variant[kNumStorages] = {-1, -1, -1, -1},
       grid[kNumStorages] = {}, nitems[kNumStorages] = {};
-  // tail launches of two-step storage types (capacity 0 otherwise)
+  // single-step tail launches of multi-step storage types (capacity 0 otherwise)
   int cap_titems[kNumStorages] = {}, tail_variant[kNumStorages] = {-1, -1, -1, -1},
       tgrid[kNumStorages] = {};
+  // two-step tail launches of three-step storage types (over the main items)
+  int pair_variant[kNumStorages] = {-1, -1, -1, -1}, p2grid[kNumStorages] = {};
   InstDesc* d_desc = nullptr;
   // Grid sized to the resident capacity, looping over the items (needed when
   // the item count changes between replays), instead of one workgroup per item.
@@ -171,8 +174,9 @@ struct BatchEngine {
   lbm_status init(hipStream_t st, int steps_per_tick, int cap_inst,
                   const int cap_items[kNumStorages], const int cap_titems[kNumStorages],
                   const int variants[kNumStorages], void* work, size_t wbytes);
-  bool two_step(int storage) const {
-    return variant[storage] >= 0 && step_variant(variant[storage]).steps == 2;
+  // Steps per launch of a storage type's step kernel.
+  int per_launch(int storage) const {
+    return variant[storage] >= 0 ? step_variant(variant[storage]).steps : 1;
   }
   // Tile used for every member instead of the members' own (-1: none).
   int tile_override = -1;
@@ -200,10 +204,10 @@ lbm_status create_ctx(const lbm_params* p, void* popA, void* popB, size_t pop_by
                       int* flag = nullptr);
 lbm_status init_droplets(lbm_ctx* c, const double* drops, int32_t n, const lbm_init* ip,
                          bool sync);
-// tail: the items of the tail launch of a two-step variant.
+// tail: the items of the single-step tail launch of a multi-step variant.
 int count_items(const std::vector<lbm_ctx*>& m, int storage, int variant, int tile_override,
                 bool tail = false);
-// Single-step shape that takes the odd last step of a tick of a two-step
+// Single-step shape that takes the last step of a tick of a multi-step
 // variant: strips of kSeriesThreads x 1 cell, 2 rows in flight.
 int tail_variant_for(int variant);
 
@@ -243,8 +247,9 @@ struct lbm_ctx {
   sclbm::InstDesc host_desc() const;
   lbm_status upload_tile(int k);
   lbm_status series_tiles();
-  // n steps with the run's tile (two-step tiles: pairs, and one single step
-  // with the series strip tile if n is odd).
+  // n steps with the run's tile (multi-step tiles: launches of K steps; two
+  // steps left over from a three-step tile in the two-step variant of the
+  // same strips, one left over in a single step with the series strip tile).
   lbm_status advance(int64_t n);
   lbm_status diagnostics(lbm_metrics* out);
   lbm_status step_series(int64_t n, int32_t every, lbm_metrics* out, int32_t* count);

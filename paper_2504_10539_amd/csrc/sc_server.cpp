@@ -113,13 +113,15 @@ struct Done {
 constexpr int kMaxBypass = 64;  // a request may be passed at most this often
 
 // Step variants and table capacities of the continuous policy's batch engine.
-// Two-step strip variants, valid for every request width: 256-thread strips
+// Multi-step strip variants, valid for every request width: 256-thread strips
 // suit the range of request sizes (64 .. 2048 columns) better than wider ones.
-// FP32 on 64-byte-aligned 240-column strips, the FP16 forms on 250-column
-// strips (per-cell shift with 2 rows in flight); a request up to 256 columns
-// wide is one periodic strip, and a tail launch takes the odd last step of a
-// tick.  Moment storage takes the 240-column strips too (its two-step kernel
-// keeps four halo columns on each side).  Item capacity: every cell of the
+// FP32 three steps per launch on 64-byte-aligned 240-column strips (the two
+// steps or the one step a tick leaves over in the two-step variant of those
+// strips or a single-step tail); the FP16 forms two steps per launch on
+// 250-column strips (per-cell shift with 2 rows in flight), a tail launch
+// taking the odd last step of a tick; a request up to 256 columns wide is one
+// periodic strip.  Moment storage takes two-step 240-column strips (its
+// two-step kernel keeps four halo columns on each side).  Item capacity: every cell of the
 // pool in the narrowest strips and shortest bands, plus a margin per slot.
 struct EngineTables {
   int cap_items[kNumStorages], cap_titems[kNumStorages], variants[kNumStorages];
@@ -127,14 +129,15 @@ struct EngineTables {
 EngineTables engine_tables(size_t pool_bytes, int max_slots) {
   EngineTables t{};
   const int v = find_variant(256, 1, 1, 0, 2, 240);
+  const int v3 = find_variant(256, 1, 1, 0, 3, 240);
   const int per = (int)std::min<size_t>(
       pool_bytes / (36ull * tile_width(v * kNumRows) * kMinRows) + 64ull * max_slots, 1u << 22);
-  const int variants[kNumStorages] = {v, find_variant(256, 1, 1, 0, 2, 250),
+  const int variants[kNumStorages] = {v3, find_variant(256, 1, 1, 0, 2, 250),
                                       find_variant(256, 1, 2, 0, 2, 250), v};
   for (int k = 0; k < kNumStorages; ++k) {
     t.variants[k] = variants[k];
     t.cap_items[k] = per;
-    t.cap_titems[k] = step_variant(variants[k]).steps == 2 ? per : 0;
+    t.cap_titems[k] = step_variant(variants[k]).steps >= 2 ? per : 0;
   }
   return t;
 }
@@ -495,7 +498,7 @@ void lbm_server::run() {
           s.left -= k;
           s.taken += k;
           s.ctx->steps += k;
-          s.ctx->parity = (int)((s.ctx->parity + tick_flips(k, eng.two_step(s.ctx->p.storage))) & 1);
+          s.ctx->parity = (int)((s.ctx->parity + tick_flips(k, eng.per_launch(s.ctx->p.storage))) & 1);
         }
       }
       if (r != LBM_OK) {
@@ -647,10 +650,10 @@ lbm_status lbm_server_create(void* pool, size_t pool_bytes, void* hip_stream,
       s->eng.persistent = true;
       s->eng.lazy_storages = true;  // no empty launches for storage types not yet served
       // One band height for every request: the persistent grid hands items out
-      // round-robin, which balances only items of similar size.  16 rows: on a
-      // saturated FP32 trace 4, 8, 16 and 32 rows served 92k, 101k, 104k and
-      // 104k MLUPS.
-      s->eng.row_override = row_choice(16);
+      // round-robin, which balances only items of similar size.  32 rows: on a
+      // saturated FP32 trace with three steps per launch 8, 16 and 32 rows
+      // served 121k, 140k and 145k MLUPS.
+      s->eng.row_override = row_choice(32);
       lbm_status r = s->eng.init(s->stream, opts->steps_per_tick, opts->max_slots, tab.cap_items,
                                  tab.cap_titems, tab.variants, s->pool + pool_bytes - eng_bytes,
                                  eng_bytes);

@@ -40,14 +40,15 @@ def _strip_tile():
 def test_multi_step_shapes_match_single_step(nx, ny):
     """Strips narrower than the halo, short and one-row bands, widths around
     the strip and workgroup widths (grids up to the workgroup's width run as
-    one periodic strip); 11 steps as 1 + 10 (three launches and a single
-    step)."""
+    one periodic strip); 16 steps as 1 + 10 + 5 (a single step; three
+    launches and a single step; one launch and the two steps left over in
+    the two-step variant of the same strips)."""
     L = lbm()
     f0 = f32_state(inputs.random_positive_state(nx, ny, seed=nx * 11 + ny))
     ref = L.Simulation(nx, ny, -5.5, 0.8)
     ref.set_tile(_strip_tile())
     set_state_from(ref, f0)
-    ref.step(11)
+    ref.step(16)
     want = to_np(ref.get_state())
     for t in _multi_step(rows=(2, 8, 128)):
         s = L.Simulation(nx, ny, -5.5, 0.8)
@@ -55,7 +56,8 @@ def test_multi_step_shapes_match_single_step(nx, ny):
         set_state_from(s, f0)
         s.step(1)
         s.step(10)
-        assert s.steps == 11
+        s.step(5)
+        assert s.steps == 16
         got = to_np(s.get_state())
         assert np.array_equal(got, want), (t, nx, ny)
         s.close()
@@ -105,23 +107,29 @@ def test_series_with_multi_step_tile_is_unchanged(k):
     assert ra == rb
 
 
-@pytest.mark.parametrize("k", [3])
-def test_batch_member_with_multi_step_tile(k):
-    """A batch takes one or two steps per launch: a member with a K-step tile
-    runs the two-step shape of the same strips, bitwise as alone."""
+@pytest.mark.parametrize("spg", [1, 2, 3, 4, 8])
+def test_batch_with_three_step_tile(spg):
+    """A batch whose FP32 members run a three-step tile: floor(K / 3) three-step
+    launches per tick of K steps, then the two steps left over in the two-step
+    variant of the same strips or the one left over in a single step.  13 and
+    then 5 steps (ticks that leave 0, 1 and 2 steps over), bitwise as alone;
+    an FP16 member beside them keeps its two-step launches."""
     L = lbm()
     mk = [lambda: L.Simulation(120, 64, -5.0, 1.0).init_droplets([(50, 30, 14)], seed=5),
-          lambda: L.Simulation(96, 96, -5.5, 0.9).init_droplets([(40, 40, 15)], seed=6)]
-    multi = _multi_step(rows=(8,), steps=(k,))[1]["id"]
+          lambda: L.Simulation(300, 96, -5.5, 0.9).init_droplets([(140, 40, 15)], seed=6),
+          lambda: L.Simulation(200, 80, -5.0, 1.0, L.LBM_F16_CELL).init_droplets([(90, 40, 12)],
+                                                                                 seed=7)]
+    multi = _multi_step(rows=(8,))[0]["id"]  # 128 threads, 112 columns
     batch = [m() for m in mk]
     solo = [m() for m in mk]
-    for s in batch:
+    for s in batch[:2]:
         s.set_tile(multi)
-    bt = L.Batch(batch, steps_per_graph=8)
-    bt.step(13)
-    for s in solo:
-        s.step(13)
-    for a, s in zip(batch, solo):
-        assert a.steps == s.steps == 13
-        assert np.array_equal(to_np(a.get_state()), to_np(s.get_state()))
+    bt = L.Batch(batch, steps_per_graph=spg)
+    for n in (13, 5):
+        bt.step(n)
+        for s in solo:
+            s.step(n)
+        for a, s in zip(batch, solo):
+            assert a.steps == s.steps
+            assert np.array_equal(to_np(a.get_state()), to_np(s.get_state())), (spg, n)
     bt.close()
