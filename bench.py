@@ -607,7 +607,7 @@ def main():
     ap.add_argument("--only", choices=["single_droplet_1024", "serving", "pinn", "sweep"],
                     default=None,
                     help="run one extra workload alone and print its result (for profiling)")
-    ap.add_argument("--graph-steps", type=int, default=32)
+    ap.add_argument("--graph-steps", type=int, default=30)
     ap.add_argument("--sweep-instances", type=int, default=512)
     ap.add_argument("--sweep-steps", type=int, default=4000)
     ap.add_argument("--serve-requests", type=int, default=2000)

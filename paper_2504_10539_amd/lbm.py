@@ -428,7 +428,7 @@ class Simulation:
 class Batch:
     """Several simulations advanced together by the batched graph."""
 
-    def __init__(self, sims: Sequence[Simulation], steps_per_graph: int = 32):
+    def __init__(self, sims: Sequence[Simulation], steps_per_graph: int = 30):
         self.sims = list(sims)
         arr = (_vp * len(self.sims))(*[s.handle for s in self.sims])
         nbytes = _sz()
@@ -466,7 +466,7 @@ class Server:
     """Continuous-batching serving loop over one pool tensor."""
 
     def __init__(self, pool_bytes: int, policy: int = LBM_POLICY_CONTINUOUS,
-                 steps_per_tick: int = 32, max_slots: int = 256, fake: bool = False,
+                 steps_per_tick: int = 30, max_slots: int = 256, fake: bool = False,
                  fake_mlups: float = 1000.0, device="cuda", stream=None):
         self.pool = None if fake else _bytes_tensor(pool_bytes, _torch().device(device))
         opts = lbm_server_opts(int(policy), int(steps_per_tick), int(max_slots), int(bool(fake)),
