@@ -303,9 +303,11 @@ lbm_status lbm_batch_work_bytes(lbm_ctx* const* ctxs, int32_t n, size_t* bytes);
  * time step (one per storage type present), `steps_per_graph` steps captured
  * in a HIP graph and replayed.  Each storage type uses the step shape of its
  * widest member's tile: with a two-step shape, one launch per two steps and a
- * single-step launch for a member's odd last step of a replay.  The per-cell arithmetic is the same
- * code as lbm_step_n, so every member's result is bitwise the one it would
- * have alone.  The contexts are borrowed and must not be stepped on their own
+ * single-step launch for a member's odd last step of a replay; with a
+ * three-step shape (LBM_F32), one launch per three steps and a two-step or a
+ * single-step launch for the steps a member has left over in a replay.  The
+ * per-cell arithmetic is the same code as lbm_step_n, so every member's
+ * result is bitwise the one it would have alone.  The contexts are borrowed and must not be stepped on their own
  * (LBM_EBUSY) until lbm_batch_destroy; metrics, moments and state copies on a
  * member stay valid.  `work` is a caller device buffer of >=
  * lbm_batch_work_bytes bytes. */

@@ -57,8 +57,8 @@ inline int tile_width(int k) {
   return v.paired ? (v.threads / 64) * kPairColumns : v.threads * v.cells;
 }
 // Columns one work item of tile shape k covers on a grid nx columns wide: a
-// two-step shape marches a grid no wider than its workgroup as one periodic
-// strip.
+// two- or three-step shape marches a grid no wider than its workgroup as one
+// periodic strip.
 inline int strip_width(int k, int nx) {
   const StepVariant& v = step_variant(tile_variant(k));
   return v.steps >= 2 && nx <= v.threads ? nx : tile_width(k);
