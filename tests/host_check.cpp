@@ -1,7 +1,9 @@
 // host_check.cpp -- drives the host side of the C-ABI (include/lbm.h) with no
 // GPU: argument validation, tile queries and the serving loop on its host-only
 // fake executor (admission, budget, bypass, early retirement of unstable
-// requests, concurrent submitters, poll, drain, destroy).  Built with the
+// requests, concurrent submitters, poll, drain, destroy), and the step
+// accounting of a batch tick for engines of one, two and three steps per
+// launch.  Built with the
 // address and undefined-behaviour sanitizers, and separately with the thread
 // sanitizer, by tests/test_host_sanitizers.py; it exits non-zero on the first
 // unexpected status.
@@ -12,6 +14,7 @@
 #include <vector>
 
 #include "lbm.h"
+#include "sc_device.h"
 
 static int g_fail = 0;
 
@@ -144,7 +147,46 @@ static void check_server(int policy) {
   EXPECT(lbm_server_destroy(s) == LBM_OK);
 }
 
+// One tick of a batch engine as its graph orders the launches (the main
+// launches, then for three steps per launch the two-step tail, then for two
+// or three the single-step tail): for every tick length T, member step count
+// nsub <= T and starting buffer, the launches that run advance the member by
+// exactly nsub steps, each reads the buffer the one before it wrote, and
+// tick_flips counts them.
+static void check_tick_accounting() {
+  using namespace sclbm;
+  for (int K = 1; K <= 3; ++K)
+    for (int T = 1; T <= 40; ++T)
+      for (int nsub = 0; nsub <= T; ++nsub)
+        for (int parity = 0; parity < 2; ++parity) {
+          InstDesc d{};
+          d.parity = parity;
+          d.nsub = nsub;
+          d.per_launch = K;
+          int steps = 0, flips = 0, buf = parity, misread = 0;
+          auto launch = [&](bool runs, int reads, int n) {
+            if (!runs) return;
+            misread += reads != buf;
+            buf ^= 1;
+            steps += n;
+            ++flips;
+          };
+          const int main_launches = K == 3 ? T / 3 : (K == 2 ? (T + 1) / 2 : T);
+          for (int j = 0; j < main_launches; ++j) {
+            if (K == 1) launch(step_runs(&d, j), step_parity(&d, j), 1);
+            if (K == 2) launch(pair_runs(&d, j), pair_parity(&d, j), 2);
+            if (K == 3) launch(multi_runs(&d, j, 3), pair_parity(&d, j), 3);
+          }
+          if (K == 3) launch(pair_runs(&d, kTail2Sub), pair_parity(&d, kTail2Sub), 2);
+          if (K >= 2) launch(step_runs(&d, kTailSub), step_parity(&d, kTailSub), 1);
+          EXPECT(steps == nsub);
+          EXPECT(misread == 0);
+          EXPECT(flips == tick_flips(nsub, K));
+        }
+}
+
 int main() {
+  check_tick_accounting();
   check_validation();
   check_server(LBM_POLICY_CONTINUOUS);
   check_server(LBM_POLICY_FIFO);

@@ -45,7 +45,9 @@ def _build(kind, out):
     for src in ("sc_runtime.cpp", "sc_server.cpp"):
         jobs.append([HIPCC, *COMMON, *san, "-c", os.path.join(CSRC, src), "-o",
                      os.path.join(out, src + ".o")])
-    jobs.append([HIPCC, "-x", "c++", *COMMON, *san, "-c", os.path.join(ROOT, "tests", "host_check.cpp"),
+    # host_check calls the host side of the kernel headers' launch accounting
+    jobs.append([HIPCC, "-x", "hip", "--offload-new-driver", "--cuda-host-only", *COMMON, *san,
+                 "-c", os.path.join(ROOT, "tests", "host_check.cpp"),
                  "-o", os.path.join(out, "host_check.o")])
     with ThreadPoolExecutor(max_workers=len(jobs)) as ex:
         list(ex.map(_run, jobs))
