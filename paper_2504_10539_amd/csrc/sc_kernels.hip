@@ -1659,8 +1659,9 @@ __global__ __launch_bounds__(kDiag2Threads) void k_step2_diag(const InstDesc* __
                                                               const int* __restrict__ nitems_p,
                                                               int sub,
                                                               double* __restrict__ partials) {
-  two_step_march<S, kDiag2Threads, 1, kDiag2Threads - kFusedHalo, true>(descs, items, nitems_p,
-                                                                       sub, partials);
+  static_assert(kDiag2Threads == kSeriesThreads, "the recording tile's workgroup");
+  constexpr int W = std::is_same<S, StoreF32>::value ? kSeries2WidthF32 : kDiag2Threads - kFusedHalo;
+  two_step_march<S, kDiag2Threads, 1, W, true>(descs, items, nitems_p, sub, partials);
 }
 
 // ============================================================== batched ticks

@@ -87,6 +87,13 @@ hipError_t launch_step_diag(int storage, const InstDesc* descs, const TileItem* 
 // kSeriesThreads threads, 1 row in flight (kSeries2Rows-row bands); `grid` =
 // number of items (one partial record each).
 constexpr int kSeries2Rows = 16;
+// Columns of the recording tile's strips: 240 for FP32 storage (strips that
+// start and end on 64-byte boundaries), kSeriesThreads - kFusedHalo for the
+// FP16 forms (storage index 0 is FP32).
+constexpr int kSeries2WidthF32 = 240;
+constexpr int series2_width(int storage) {
+  return storage == 0 ? kSeries2WidthF32 : kSeriesThreads - kFusedHalo;
+}
 hipError_t launch_step2_diag(int storage, const InstDesc* descs, const TileItem* items,
                              const int* nitems, int grid, int sub, double* partials, double* out,
                              hipStream_t st);

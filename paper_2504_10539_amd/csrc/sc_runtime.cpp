@@ -88,9 +88,9 @@ WorkLayout work_layout(int nx, int ny) {
   // the series tile: kSeriesThreads-wide strips, row index 0 (8-row bands)
   w.series_items = ((nx + kSeriesThreads - 1) / kSeriesThreads) *
                    ((ny + kRowChoices[0] - 1) / kRowChoices[0]);
-  // and the two-step recording tile: kSeriesThreads - kFusedHalo columns,
-  // kSeries2Rows-row bands
-  const int w2 = kSeriesThreads - kFusedHalo;
+  // and the two-step recording tile: strips of series2_width columns (the
+  // narrowest, FP32's, sizes the table), kSeries2Rows-row bands
+  const int w2 = kSeries2WidthF32;
   w.series2_items = ((nx + w2 - 1) / w2) * ((ny + kSeries2Rows - 1) / kSeries2Rows);
   w.s_nitems = o;
   o += 256;
@@ -439,7 +439,8 @@ lbm_status lbm_ctx::series_tiles() {
   lbm_status r = build(find_variant(kSeriesThreads, 1, 2, 0) * kNumRows + row_choice(8),
                        lay.series_items, d_sitems, d_snitems, &n1);
   if (r == LBM_OK)
-    r = build(find_variant(kSeriesThreads, 1, 1, 0, 2) * kNumRows + row_choice(kSeries2Rows),
+    r = build(find_variant(kSeriesThreads, 1, 1, 0, 2, series2_width(p.storage)) * kNumRows +
+                  row_choice(kSeries2Rows),
               lay.series2_items, d_s2items, d_s2nitems, &n2);
   if (r != LBM_OK) return r;
   SCLBM_HIP(hipStreamSynchronize(stream));
