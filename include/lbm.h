@@ -330,7 +330,7 @@ lbm_status lbm_batch_destroy(lbm_batch* b);
 /* ------------------------------------------------------------ serving */
 
 #define LBM_POLICY_CONTINUOUS 0  /* continuous batching: admit while memory and slots allow */
-#define LBM_POLICY_FIFO 1        /* plain path: one simulation at a time, per-step launches */
+#define LBM_POLICY_FIFO 1        /* plain path: one simulation at a time, its own tile shape */
 
 typedef struct lbm_server_opts {
   int32_t policy;          /* LBM_POLICY_CONTINUOUS or LBM_POLICY_FIFO */
