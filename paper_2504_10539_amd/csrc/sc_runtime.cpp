@@ -449,6 +449,12 @@ lbm_status lbm_ctx::series_tiles() {
   return LBM_OK;
 }
 
+// Two-step variant of the same strips as three-step variant v (-1 for others).
+static int pair_variant_for(int v) {
+  const StepVariant& sv = step_variant(v);
+  return sv.steps == 3 ? find_variant(sv.threads, 1, sv.prefetch, 0, 2, sv.width) : -1;
+}
+
 lbm_status lbm_ctx::advance(int64_t n) {
   const int v = tile_variant(tile);
   const int per = tile_steps(tile);
@@ -460,8 +466,7 @@ lbm_status lbm_ctx::advance(int64_t n) {
   if (n >= 2) {
     // two steps left after three-step launches: the two-step variant of the
     // same strips, over the same work items
-    const StepVariant& tv = step_variant(v);
-    const int v2 = find_variant(tv.threads, 1, tv.prefetch, 0, 2, tv.width);
+    const int v2 = pair_variant_for(v);
     if (v2 < 0) return fail(LBM_EDEVICE, "no two-step variant for a three-step tile");
     SCLBM_HIP(launch_step(p.storage, v2, d_desc, d_items, d_nitems, nitems, parity, stream));
     parity ^= 1;
@@ -560,11 +565,6 @@ int tail_variant_for(int variant) {
   return step_variant(variant).steps >= 2 ? find_variant(kSeriesThreads, 1, 2, 0) : -1;
 }
 
-// Two-step variant of the same strips as three-step variant v (-1 for others).
-static int pair_variant_for(int v) {
-  const StepVariant& sv = step_variant(v);
-  return sv.steps == 3 ? find_variant(sv.threads, 1, sv.prefetch, 0, 2, sv.width) : -1;
-}
 
 lbm_status BatchEngine::init(hipStream_t st, int steps_per_tick, int cap_inst_,
                              const int cap_items_[kNumStorages],
