@@ -396,16 +396,22 @@ class Simulation:
     def autotune(self, reps: int = 5, stepping: bool = True) -> int:
         """Selects the fastest tile shape.  stepping=True times the shapes as
         the run steps (lbm_autotune_stepping, with a scratch copy of the state
-        allocated here for the call); False times repeated launches over the
-        unchanged state (lbm_autotune)."""
+        allocated here for the call; where the device has no room for it, the
+        shapes are timed over the unchanged state instead); False times
+        repeated launches over the unchanged state (lbm_autotune)."""
         best = _i32()
-        if not stepping:
-            _check(LIB.lbm_autotune(self.handle, int(reps), ctypes.byref(best)), "lbm_autotune")
-            return best.value
         pop = _sz()
         _check(LIB.lbm_buffer_bytes(ctypes.byref(self.params), ctypes.byref(pop), None),
                "lbm_buffer_bytes")
-        scratch = _bytes_tensor(pop.value, self.device)
+        scratch = None
+        if stepping:
+            try:
+                scratch = _bytes_tensor(pop.value, self.device)
+            except _torch().cuda.OutOfMemoryError:
+                scratch = None
+        if scratch is None:
+            _check(LIB.lbm_autotune(self.handle, int(reps), ctypes.byref(best)), "lbm_autotune")
+            return best.value
         _check(LIB.lbm_autotune_stepping(self.handle, int(reps), _dev_ptr(scratch), pop.value,
                                          ctypes.byref(best)), "lbm_autotune_stepping")
         del scratch

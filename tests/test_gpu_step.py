@@ -240,3 +240,21 @@ def test_stepping_autotune_refuses_bad_scratch():
     assert L.LIB.lbm_autotune_stepping(s.handle, 1, None, pop.value, ctypes.byref(best)) == L.LBM_EINVAL
     assert L.LIB.lbm_autotune_stepping(s.handle, 0, buf.data_ptr(), pop.value,
                                        ctypes.byref(best)) == L.LBM_EINVAL
+
+
+def test_stepping_autotune_without_room_for_scratch(tmp_path, monkeypatch):
+    """Where the device has no room for the scratch copy, the binding times
+    the shapes over the unchanged state instead (and still picks one)."""
+    monkeypatch.setenv("SCLBM_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    L = lbm()
+    s = L.Simulation(96, 64, -5.0, 1.0).init_droplets([(40.0, 30.0, 12.0)], seed=2)
+    s.step(2)
+    before = s.get_state().clone()
+
+    def no_room(nbytes, device):
+        raise torch.cuda.OutOfMemoryError("no room")
+
+    monkeypatch.setattr(L, "_bytes_tensor", no_room)
+    best = s.autotune(reps=1)
+    assert 0 <= best < len(L.tiles()) and s.tile == best and s.steps == 2
+    assert torch.equal(s.get_state(), before)
